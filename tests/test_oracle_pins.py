@@ -1,0 +1,334 @@
+"""Pins of the CPU oracle against what the thesis and the mathematics fix.
+
+Each check comes from outside the oracle's own code: the thesis's worked
+examples (tests/golden), closed forms, textbook special cases, brute force on
+tiny inputs, and invariants that a dropped term, a wrong sign or a transposed
+operand would break."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import pairgen
+from tests.conftest import read_golden
+
+enc = pairgen.encode
+
+
+# ---------------------------------------------------------------- worked examples
+def test_sneakysnake_fig8_worked_example():
+    g = read_golden("sneakysnake_fig8.txt")
+    ref, read, E = g["ref"], g["read"], int(g["E"])
+    acc, cnt, pipes = oracle.sneakysnake(enc(read), enc(ref), E, with_pipes=True)
+    assert acc == bool(int(g["accept"]))
+    assert cnt == int(g["obstacles"])
+    # The bases each followed pipe covers (columns run along the reference).
+    spelled = [ref[c:c + L] for (c, d, L) in pipes]
+    assert spelled == g["pipes"].split(",")
+    # The reference bases of each pipe equal the read bases on its diagonal.
+    for c, d, L in pipes:
+        assert ref[c:c + L] == read[c + d:c + d + L]
+
+
+def test_sneakysnake_orientation_matters():
+    # Traversing along the read (swapping the roles) gives other pipes, so the
+    # worked example does fix the orientation.
+    g = read_golden("sneakysnake_fig8.txt")
+    _, _, pipes = oracle.sneakysnake(enc(g["ref"]), enc(g["read"]), int(g["E"]), with_pipes=True)
+    spelled = [g["read"][c:c + L] for (c, d, L) in pipes]
+    assert spelled != g["pipes"].split(",")
+
+
+def test_shouji_fig6_worked_example():
+    g = read_golden("shouji_fig6.txt")
+    T, P, E = g["text"], g["pattern"], int(g["E"])
+    acc, cnt, S = oracle.shouji(enc(P), enc(T), E, with_vector=True)
+    runs = []
+    c = 0
+    while c < len(S):
+        if S[c] == "0":
+            a = c
+            while c < len(S) and S[c] == "0":
+                c += 1
+            runs.append(T[a:c])
+        else:
+            c += 1
+    assert runs == g["common"].split(",")
+    assert cnt == len(T) - sum(len(r) for r in runs)
+    assert acc
+
+
+def test_levenshtein_not_additive_example():
+    g = read_golden("prefix_cgcg.txt")
+    a, b = enc(g["a"]), enc(g["b"])
+    assert oracle.hamming(a, b) == int(g["per_base"])
+    assert oracle.levenshtein(a, b) == int(g["distance"])
+    assert oracle.banded_levenshtein(a, b, 2) == int(g["distance"])
+    assert oracle.banded_levenshtein(a, b, 1) == 2  # band of 1 also reaches 2 (shift by one)
+
+
+def test_amend_rules():
+    with open("tests/golden/amend_srs.txt") as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            src, dst = [s.strip() for s in line.split("->")]
+            got = oracle.amend(np.array([int(ch) for ch in src], np.uint8))
+            assert "".join(str(int(v)) for v in got) == dst, src
+
+
+def test_lzc_tile_example_as_single_diagonal():
+    g = read_golden("lzc_tile.txt")
+    row = g["row_msb_first"][::-1]          # column c = bit c
+    m = len(row)
+    # Periodic ACGT reference: every shifted comparison mismatches, so only the
+    # main diagonal carries pipes.  Read = reference with a substitution at
+    # each 1-bit, chosen to match neither neighbour diagonal.
+    ref = [i % 4 for i in range(m)]
+    read = list(ref)
+    for c, bit in enumerate(row):
+        if bit == "1":
+            read[c] = (ref[c] + 2) % 4
+    acc, cnt, pipes = oracle.sneakysnake(np.array(read), np.array(ref), 1, with_pipes=True)
+    assert [L for (_, d, L) in pipes] == [int(x) for x in g["pipes"].split(",")]
+    assert all(d == 0 for (_, d, _) in pipes)
+    assert cnt == int(g["obstacles"]) and acc
+
+
+# ---------------------------------------------------------------- Levenshtein
+def _bfs_distance(a, b, limit):
+    """Edit distance by breadth-first search over single-edit neighbours (a
+    route that shares nothing with the dynamic programme); None if > limit."""
+    a, b = tuple(a), tuple(b)
+    if a == b:
+        return 0
+    frontier, seen = {a}, {a}
+    for depth in range(1, limit + 1):
+        nxt = set()
+        for s in frontier:
+            n = len(s)
+            cands = []
+            for i in range(n):
+                cands.append(s[:i] + s[i + 1:])
+                for x in range(4):
+                    if x != s[i]:
+                        cands.append(s[:i] + (x,) + s[i + 1:])
+            for i in range(n + 1):
+                for x in range(4):
+                    cands.append(s[:i] + (x,) + s[i:])
+            for t in cands:
+                if t == b:
+                    return depth
+                if t not in seen:
+                    seen.add(t)
+                    nxt.add(t)
+        frontier = nxt
+    return None
+
+
+def test_levenshtein_against_bfs():
+    rng = np.random.default_rng(1)
+    for _ in range(300):
+        m = int(rng.integers(1, 6))
+        a = rng.integers(0, 4, m)
+        # b: a with up to 3 random edits, so short distances are well covered
+        b = list(a)
+        for _ in range(int(rng.integers(0, 4))):
+            kind = rng.integers(0, 3)
+            if kind == 0 and b:
+                i = rng.integers(0, len(b)); b[i] = (b[i] + 1 + rng.integers(0, 3)) % 4
+            elif kind == 1:
+                b.insert(int(rng.integers(0, len(b) + 1)), int(rng.integers(0, 4)))
+            elif b:
+                b.pop(int(rng.integers(0, len(b))))
+        d = _bfs_distance(a, b, 2)
+        got = oracle.levenshtein(np.array(a), np.array(b, dtype=np.uint8))
+        if d is None:
+            assert got > 2
+        else:
+            assert got == d
+
+
+def test_banded_equals_full_within_band():
+    rng = np.random.default_rng(2)
+    for _ in range(400):
+        m = int(rng.integers(1, 20))
+        a = rng.integers(0, 4, m)
+        b = a.copy()
+        for _ in range(int(rng.integers(0, 6))):
+            b[int(rng.integers(0, m))] = rng.integers(0, 4)
+        if rng.random() < 0.5 and m > 2:  # an indel pair keeping the length
+            i, j = sorted(rng.integers(0, m, 2))
+            b = np.concatenate([b[:i], b[i + 1:j + 1], [rng.integers(0, 4)], b[j + 1:]])[:m]
+        E = int(rng.integers(0, 6))
+        full = oracle.levenshtein(a, b)
+        band = oracle.banded_levenshtein(a, b, E)
+        if full <= E:
+            assert band == full
+        else:
+            assert band == E + 1
+        assert band <= E + 1
+
+
+# ---------------------------------------------------------------- SneakySnake
+def _all_pairs(m):
+    seqs = np.array(list(itertools.product(range(4), repeat=m)), np.uint8)
+    idx = np.array(list(itertools.product(range(len(seqs)), repeat=2)))
+    return seqs[idx[:, 0]], seqs[idx[:, 1]]
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4])
+def test_sneakysnake_never_rejects_within_E_exhaustive(m):
+    reads, refs = _all_pairs(m)
+    n = reads.shape[0]
+    for E in range(0, m + 2):
+        ss = oracle.filter_batch(reads, refs, np.full(n, m), np.full(n, E))[1]
+        band = oracle.banded_batch(reads, refs, np.full(n, m), np.full(n, E))
+        acc, cnt = ss
+        # Lower bound: the obstacle count never exceeds the banded distance.
+        assert np.all(cnt.astype(int) <= band.astype(int))
+        # Hence zero false rejects.
+        assert np.all(acc[band <= E] == 1)
+        assert np.all((cnt <= E) == (acc == 1))
+
+
+def test_sneakysnake_lower_bound_random_16():
+    rng = np.random.default_rng(3)
+    n, m = 20000, 16
+    reads = rng.integers(0, 4, (n, m)).astype(np.uint8)
+    refs = reads.copy()
+    for i in range(n):
+        for _ in range(rng.integers(0, 5)):
+            kind = rng.integers(0, 3)
+            r = list(refs[i])
+            if kind == 0:
+                j = rng.integers(0, m); r[j] = (r[j] + 1 + rng.integers(0, 3)) % 4
+            elif kind == 1:
+                r.insert(int(rng.integers(0, m + 1)), int(rng.integers(0, 4))); r = r[:m]
+            else:
+                r.pop(int(rng.integers(0, m))); r.append(int(rng.integers(0, 4)))
+            refs[i] = r
+    for E in (0, 1, 2, 3, 5):
+        acc, cnt = oracle.filter_batch(reads, refs, np.full(n, m), np.full(n, E))[1]
+        band = oracle.banded_batch(reads, refs, np.full(n, m), np.full(n, E))
+        assert np.all(cnt.astype(int) <= band.astype(int))
+        assert np.all(acc[band <= E] == 1)
+
+
+def test_sneakysnake_E0_is_hamming_capped():
+    # With one diagonal the snake stops at the first mismatch: min(H, 1).
+    p = pairgen.generate(pairgen.SMALL_100BP, 0, 3000)
+    acc, cnt = oracle.filter_batch(p.reads, p.refs, p.len, 0)[1]
+    ham = (p.reads != p.refs).sum(1)
+    assert np.array_equal(cnt, np.minimum(ham, 1))
+    assert np.array_equal(acc, (ham == 0).astype(np.uint8))
+
+
+def test_sneakysnake_bounded_by_hamming_and_identical_zero():
+    p = pairgen.generate(pairgen.SMALL_100BP, 0, 3000)
+    for E in (1, 5, 12):
+        acc, cnt = oracle.filter_batch(p.reads, p.refs, p.len, E)[1]
+        ham = (p.reads != p.refs).sum(1)
+        assert np.all(cnt <= np.minimum(ham, E + 1))
+    acc, cnt = oracle.filter_batch(p.reads, p.reads, p.len, 5)[1]
+    assert np.all(cnt == 0) and np.all(acc == 1)
+
+
+def test_weighted_equals_unweighted():
+    p = pairgen.generate(pairgen.FIXED_250BP, 0, 600)
+    for i in range(p.n):
+        for E in (0, 3, 10):
+            a = oracle.sneakysnake(p.reads[i], p.refs[i], E)
+            b = oracle.sneakysnake_weighted(p.reads[i], p.refs[i], E)
+            assert a == b
+
+
+def test_sneakysnake_monotone_in_E():
+    p = pairgen.generate(pairgen.FIXED_250BP, 0, 4000)
+    prev = None
+    for E in range(0, 16):
+        acc, _ = oracle.filter_batch(p.reads, p.refs, p.len, E)[1]
+        if prev is not None:
+            assert np.all(acc >= prev)
+        prev = acc
+
+
+def test_sneakysnake_E_at_least_m_accepts():
+    p = pairgen.generate(pairgen.SMALL_100BP, 0, 200)
+    short = p.reads[:, :7].copy(), p.refs[:, :7].copy()
+    acc, cnt = oracle.filter_batch(short[0], short[1], np.full(200, 7), 7)[1]
+    # 2E+1 diagonals cover every cell; the greedy needs at most m - 1 ... but
+    # the count is still bounded by the banded distance <= m.
+    band = oracle.banded_batch(short[0], short[1], np.full(200, 7), 7)
+    assert np.all(acc[band <= 7] == 1)
+
+
+# ---------------------------------------------------------------- GateKeeper
+def test_gatekeeper_E0_is_exact_match():
+    p = pairgen.generate(pairgen.SMALL_100BP, 0, 3000)
+    acc, cnt = oracle.filter_batch(p.reads, p.refs, p.len, 0, oracle.GATEKEEPER)[2]
+    ham = (p.reads != p.refs).sum(1)
+    assert np.array_equal(acc, (ham == 0).astype(np.uint8))
+
+
+def test_gatekeeper_fast_path_and_amended_count():
+    # Substitution-only pair whose Hamming distance is <= E: Method 1 accepts
+    # with count = Hamming distance.
+    rng = np.random.default_rng(5)
+    a = rng.integers(0, 4, 100).astype(np.uint8)
+    b = a.copy()
+    for j in (10, 40, 77):
+        b[j] = (b[j] + 1) % 4
+    assert oracle.gatekeeper(a, b, 3) == (True, 3)
+    # E = 0 on a pair whose main-diagonal mask is 1 0 1 0 0 1 ...: the reject
+    # count is the popcount of the amended mask (Sec. 5.2.2 rule).
+    mask = np.array([int(c) for c in "0110100111000101"], np.uint8)
+    ref = np.zeros(mask.size, np.uint8)
+    read = (ref + mask).astype(np.uint8)
+    acc, cnt = oracle.gatekeeper(read, ref, 0)
+    # Hand-amended: zeros at 3 (101), 5-6 (1001) and 14 (101) flip; 10-12 (a
+    # run of 3) stays, and so does 0, which touches the start.
+    assert not acc and cnt == sum(int(c) for c in "0111111111000111")
+
+
+def test_gatekeeper_identical_is_zero():
+    p = pairgen.generate(pairgen.SMALL_100BP, 0, 300)
+    acc, cnt = oracle.filter_batch(p.reads, p.reads, p.len, 5, oracle.GATEKEEPER)[2]
+    assert np.all(cnt == 0) and np.all(acc == 1)
+
+
+# ---------------------------------------------------------------- Shouji
+def test_shouji_E0_is_hamming():
+    p = pairgen.generate(pairgen.SMALL_100BP, 0, 3000)
+    acc, cnt = oracle.filter_batch(p.reads, p.refs, p.len, 0, oracle.SHOUJI)[4]
+    ham = (p.reads != p.refs).sum(1)
+    assert np.array_equal(cnt.astype(int), ham)
+
+
+def test_shouji_identical_is_zero_and_count_le_m():
+    p = pairgen.generate(pairgen.SMALL_100BP, 0, 300)
+    acc, cnt = oracle.filter_batch(p.reads, p.reads, p.len, 5, oracle.SHOUJI)[4]
+    assert np.all(cnt == 0)
+    acc, cnt = oracle.filter_batch(p.reads, p.refs, p.len, 5, oracle.SHOUJI)[4]
+    assert np.all(cnt <= 100)
+
+
+# ---------------------------------------------------------------- features
+def test_features_closed_form():
+    # All-A pair of length 10, E = 3: every in-range cell matches, so the match
+    # fraction of diagonal d is (10 - |d|) / 10.
+    a = np.zeros(10, np.uint8)
+    f = oracle.features(a, a, 3)
+    assert f[0] == 10 / 512 and f[1] == 3 / 32
+    for d in range(-3, 4):
+        assert f[32 + d] == pytest.approx((10 - abs(d)) / 10)
+    assert np.count_nonzero(f) == 2 + 7
+    # Only the first 64 columns count: a 100-base pair that differs only after
+    # column 64 has main-diagonal fraction 1.
+    rng = np.random.default_rng(0)
+    x = rng.integers(0, 4, 100).astype(np.uint8)
+    y = x.copy()
+    y[70:] = (y[70:] + 1) % 4
+    assert oracle.features(x, y, 5)[32] == 1.0
