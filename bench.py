@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark of the pre-alignment filter path on one MI355X.
+
+Workload: 10M synthetic (read, reference segment) pairs of 250 bp, 2-bit
+packed and resident in HBM, E = 10 (70% unrelated segments, related ones with
+k ~ U{0..40} random edits).  One step = one pass of the filter over the whole
+batch: load, map build, SneakySnake traversal, decision and output writes.
+
+Prints one JSON line.  `roofline` is for the filter kernel (algorithmic bytes:
+both packed sequences in, counts and accept bits out), timed with HIP events
+on the stream the kernel runs on; `cpu_baseline` is the CPU oracle on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def build_batch(ctx, w, n, dev, chunk=2_000_000):
+    """Generate pairs [0, n) of workload w chunk by chunk and pack them on the GPU."""
+    import torch
+
+    import pairgen
+    import paper_1910_03936_amd as paf
+
+    m = w.lens[0]
+    stride = paf.words_for(m)
+    rd = torch.empty(n * stride, dtype=torch.int64, device=dev)
+    rf = torch.empty(n * stride, dtype=torch.int64, device=dev)
+    first = None
+    for a in range(0, n, chunk):
+        q = pairgen.generate(w, a, min(chunk, n - a))
+        if first is None:
+            first = q
+        r = ctx.pack(torch.from_numpy(q.reads).to(dev), uniform_len=m, stride_words=stride)
+        f = ctx.pack(torch.from_numpy(q.refs).to(dev), uniform_len=m, stride_words=stride)
+        rd[a * stride:(a + q.n) * stride] = r
+        rf[a * stride:(a + q.n) * stride] = f
+        del r, f
+    torch.cuda.synchronize()
+    ctx.check()
+    E = w.fixed_E
+    b = paf.Batch(rd, rf, n, stride, uniform_len=m, uniform_E=E, max_len=m, max_E=E)
+    return b, first
+
+
+def time_steps(fn, steps, warmup):
+    """Per-step HIP event times (ms) on the current stream, plus the total."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(s)
+    for a, b in ev:
+        a.record(s)
+        fn()
+        b.record(s)
+    t1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    per = [a.elapsed_time(b) for a, b in ev]
+    return per, t0.elapsed_time(t1), wall
+
+
+def traffic_record(kernel_src: str, key: str):
+    """HBM bytes per launch measured with rocprofv3 counters, if they were taken
+    on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    r = rec.get(key)
+    if not r or r.get("kernel_sha256_16") != h:
+        return None
+    return r
+
+
+def cpu_baseline(sample, E, budget_s=15.0):
+    """The oracle (as is) on host threads over a bounded sample of the workload."""
+    import numpy as np
+
+    import oracle
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    n0 = min(sample.n, 50_000)
+    t = time.perf_counter()
+    oracle.filter_batch(sample.reads[:n0], sample.refs[:n0], sample.len[:n0], E, oracle.SNEAKYSNAKE,
+                        threads=threads)
+    dt = time.perf_counter() - t
+    n = int(min(sample.n, max(n0, n0 * budget_s / max(dt, 1e-6))))
+    t = time.perf_counter()
+    oracle.filter_batch(sample.reads[:n], sample.refs[:n], sample.len[:n], E, oracle.SNEAKYSNAKE,
+                        threads=threads)
+    dt = time.perf_counter() - t
+    return {"value": n / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} pairs of the workload, SneakySnake only, {dt:.1f} s on {threads} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--pairs", type=int, default=None, help="override the batch size (default 10M)")
+    ap.add_argument("--E", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}): this build has no "
+              f"multi-GPU path; pairs are independent, so a multi-GPU run would shard the batch "
+              f"(see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import pairgen
+    import paper_1910_03936_amd as paf
+
+    dev = torch.device("cuda", 0)
+    ctx = paf.Context(0)
+    w = pairgen.FIXED_250BP.with_E(args.E)
+    n = args.pairs or w.n_pairs
+    t = time.perf_counter()
+    batch, first = build_batch(ctx, w, n, dev)
+    log(f"generated and packed {n} pairs in {time.perf_counter() - t:.1f} s")
+
+    out = ctx.alloc_out(n, paf.SNEAKYSNAKE, dev)
+    per, total_ms, wall = time_steps(lambda: ctx.filter(batch, paf.SNEAKYSNAKE, out=out),
+                                     args.steps, args.warmup)
+    ctx.check()
+    ms = total_ms / args.steps
+    kern_ms = sum(per) / len(per)
+    value = n / (ms / 1e3)
+    log(f"plain: {ms:.3f} ms/step, kernel {kern_ms:.3f} ms, {value / 1e9:.2f} G pairs/s")
+
+    W = paf.words_for(250)
+    alg_bytes = n * (2 * W * 8 + 2 + 1 / 8)
+    achieved = alg_bytes / (kern_ms / 1e3) / 1e9
+    tr = traffic_record(os.path.join(ROOT, "paper_1910_03936_amd", "csrc", "filter.hip"),
+                        f"snake_plain_250bp_E{args.E}")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if tr is None else tr["bytes_per_launch"] * n / tr["n_pairs"],
+                "kernel": "filter_kernel<Snake, E=10, plain>",
+                "alg_bytes_per_pair": round(2 * W * 8 + 2 + 1 / 8, 3)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t = time.perf_counter()
+        cpu = cpu_baseline(first, args.E)
+        log(f"cpu baseline {cpu['value']:.3g} pairs/s ({time.perf_counter() - t:.1f} s)")
+
+    rec = {
+        "metric": "filtered pairs/sec at 250bp E=10, learned-bucketed vs plain; HBM GB/s %peak",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"{n} pairs, 250 bp, 2-bit packed, E={args.E}, 70% unrelated, "
+                               f"k~U{{0..40}}; SneakySnake, plain batched launch",
+                   "pairs": n, "read_len": 250, "E": args.E, "filters": "sneakysnake",
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

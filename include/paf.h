@@ -1,0 +1,199 @@
+/*
+ * paf.h -- C ABI of libpaf, an MI355X (gfx950) library for pre-alignment
+ * filtering of (read, reference segment) pairs under an edit threshold E,
+ * after Alser's thesis "Accelerating the Understanding of Life's Code Through
+ * Better Algorithms and Hardware Design" (arXiv 1910.03936).
+ *
+ * General conventions
+ *  - Every pointer marked [device] is device memory owned by the caller; the
+ *    library never frees it.  [host] pointers are host memory.
+ *  - Calls that take a `stream` (a hipStream_t passed as void*, NULL = the
+ *    null stream) are asynchronous: they enqueue work and return.  The caller
+ *    synchronizes before reading outputs.
+ *  - Every call validates its arguments on the host before launching
+ *    anything; on a bad argument it returns PAF_ERR_ARG or PAF_ERR_RANGE,
+ *    launches nothing and leaves a message for paf_last_error().  Per-pair
+ *    values that live in device memory (lengths, thresholds) are checked by
+ *    the kernels; a violation sets a sticky flag in the context, the pair's
+ *    outputs are zero, and the next paf_check() reports PAF_ERR_RANGE.
+ *  - No C++ exception crosses this interface.
+ *  - A context serves one device; calls on one context from several threads
+ *    must be serialized by the caller.
+ *
+ * Sequence encoding (Ch. 5, Method 3: two bits per base; the thesis fixes
+ * A = 00 and T = 11, this library uses C = 01 and G = 10).  A sequence of m
+ * bases occupies ceil(m / 32) uint64 words; word k holds bases 32k..32k+31
+ * with the low code bit of base 32k+j in bit j and the high code bit in bit
+ * 32 + j.  Bases past m are zero.  paf_pack / paf_pack_host produce this.
+ */
+#ifndef PAF_H
+#define PAF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct paf_ctx paf_ctx;
+
+typedef enum {
+    PAF_OK = 0,
+    PAF_ERR_ARG = 1,     /* NULL pointer, zero size, inconsistent arguments */
+    PAF_ERR_RANGE = 2,   /* length, threshold or size outside the supported range */
+    PAF_ERR_DEVICE = 3,  /* a HIP runtime call failed */
+    PAF_ERR_NOMEM = 4,   /* device or pinned allocation failed */
+    PAF_ERR_STATE = 5    /* call out of order (e.g. predicting with no model) */
+} paf_status;
+
+/* Filter selection mask; the bit position is also the index into paf_out. */
+enum { PAF_SNEAKYSNAKE = 1u, PAF_GATEKEEPER = 2u, PAF_SHOUJI = 4u };
+
+#define PAF_MAX_LEN 512  /* bases per sequence: 16 words */
+#define PAF_MAX_E 31     /* threshold: 2E+1 <= 63 diagonals */
+
+/* A batch of pairs (all pointers [device]).
+ * Pair p: read words at reads + off(p), reference words at refs + off(p),
+ * off(p) = word_offset[p] if word_offset != NULL else p * stride_words.
+ * Length m(p) = len[p] if len != NULL else uniform_len, 1 <= m <= PAF_MAX_LEN.
+ * Threshold E(p) = E[p] if E != NULL else uniform_E, 0 <= E <= PAF_MAX_E.
+ * max_len / max_E: upper bounds over the batch (equal to the uniform values
+ * when those are used); the kernels are specialised on them, and a pair
+ * above them is a device-side range violation. */
+typedef struct {
+    const uint64_t* reads;
+    const uint64_t* refs;
+    const uint64_t* word_offset;
+    uint32_t stride_words;
+    const uint16_t* len;
+    uint16_t uniform_len;
+    const uint8_t* E;
+    uint8_t uniform_E;
+    uint16_t max_len;
+    uint8_t max_E;
+    uint64_t n_pairs;
+} paf_batch;
+
+/* Outputs (all [device]).  Index 0 = SneakySnake, 1 = GateKeeper,
+ * 2 = Shouji.  accept_bits[f] holds ceil(n/32) words: pair p's decision is
+ * bit p % 32 of word p / 32 (1 = accept, i.e. pass on to alignment).
+ * count[f] holds n uint16: SneakySnake's obstacle count min(e, E+1);
+ * GateKeeper's and Shouji's edit estimate (the ones they counted).  A filter
+ * requested in the mask needs both of its pointers; the others may be NULL. */
+typedef struct {
+    uint32_t* accept_bits[3];
+    uint16_t* count[3];
+} paf_out;
+
+/* Context: binds device `device`, allocates the small device state (error
+ * flag, work-queue counter, model weights, autotune cache).  *ctx is NULL on
+ * failure. */
+paf_status paf_create(paf_ctx** ctx, int device);
+paf_status paf_destroy(paf_ctx* ctx);
+
+/* Thread-local message describing the last non-OK status of this thread. */
+const char* paf_last_error(void);
+
+/* Waits for `stream`, then reports (and clears) the sticky device-side range
+ * flag: PAF_ERR_RANGE if any pair since the last check had a length or
+ * threshold outside its batch's bounds. */
+paf_status paf_check(paf_ctx* ctx, void* stream);
+
+/* Step a1 -- encode (Ch. 4 host read encoder; Ch. 5 Method 3).
+ * codes [device]: n rows of code_stride bytes, base values 0..3 (A,C,G,T);
+ * row p holds m(p) bases (len/uniform_len as in paf_batch).
+ * words [device]: output, written at off(p) as in paf_batch; the caller
+ * sizes it.  A code above 3 sets the sticky range flag. */
+paf_status paf_pack(paf_ctx* ctx, const uint8_t* codes, uint32_t code_stride, const uint16_t* len,
+                    uint16_t uniform_len, const uint64_t* word_offset, uint32_t stride_words,
+                    uint64_t n, uint64_t* words, void* stream);
+
+/* Host-side encoder with the same layout (for streaming from host memory).
+ * All pointers [host].  Uses up to `threads` host threads (0 = library
+ * default).  Returns PAF_ERR_RANGE on a code above 3 or a bad length. */
+paf_status paf_pack_host(const uint8_t* codes, uint32_t code_stride, const uint16_t* len,
+                         uint16_t uniform_len, const uint64_t* word_offset, uint32_t stride_words,
+                         uint64_t n, uint64_t* words, int threads);
+
+/* Steps a2-a7 -- plain batched filter.  For every pair: stage its words,
+ * build the 2E+1 diagonal match bit-vectors (neighbourhood map, Eq. 6.1 /
+ * unweighted maze, Eq. 8.2) and run the requested decision stages on them:
+ * SneakySnake's greedy traversal (Ch. 8, Sec. 8.4), GateKeeper's Hamming
+ * fast path plus amended shifted masks (Ch. 5, Sec. 5.2) and Shouji's
+ * sliding-window search (Ch. 6, Sec. 6.2).  filters: mask of PAF_* bits. */
+paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, const paf_out* out,
+                      void* stream);
+
+/* Step a8 -- the same filter as one persistent launch over a work queue of
+ * 64-pair tiles (the Read Controller's role, Sec. 4.2.1), for batches of
+ * uneven lengths and per-pair thresholds.  The launch (queue reset + kernel)
+ * is captured once into a HIP graph per (layout, filters, bounds, stream)
+ * and replayed; the layout is the one paf_autotune chose for this batch's
+ * (max_len, max_E, filters) class, else the default.  Outputs as
+ * paf_filter. */
+paf_status paf_filter_persistent(paf_ctx* ctx, const paf_batch* batch, uint32_t filters,
+                                 const paf_out* out, void* stream);
+
+/* Layout of the persistent filter. */
+typedef struct {
+    uint32_t lanes_per_pair;   /* 1 (pair per lane) */
+    uint32_t waves_per_block;  /* 1, 2, 4 or 8 */
+    uint32_t blocks_per_cu;    /* resident blocks per compute unit in the persistent grid */
+    uint32_t tiles_per_grab;   /* 64-pair tiles taken per queue access */
+} paf_layout;
+
+/* Times each candidate layout on `batch` (synchronously, on `stream`),
+ * caches the fastest for the batch's class and returns it (and, if not NULL,
+ * the time of the fastest and of the default layout in ms).  Outputs in
+ * `out` are overwritten. */
+paf_status paf_autotune(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, const paf_out* out,
+                        void* stream, paf_layout* chosen, float* best_ms, float* default_ms);
+paf_status paf_set_layout(paf_ctx* ctx, const paf_layout* layout); /* NULL = back to autotuned */
+
+/* Step a9 -- learned cost bucketing.
+ * Features of each pair (fp32, 64 per pair, row-major [n][64]): [0] = m/512,
+ * [1] = E/32, slot 32+d = fraction of matching map cells over the first
+ * min(m, 64) columns of diagonal d, |d| <= min(E, 30); other slots 0. */
+paf_status paf_features(paf_ctx* ctx, const paf_batch* batch, float* features, void* stream);
+
+/* Cost model: dense 64 -> 128 -> 128 -> 1, ReLU on the hidden layers.
+ * Parameters are fp32 master copies with bf16 working copies used by the
+ * matrix-core kernels (fp32 accumulation).  Host layout of `params`
+ * (PAF_MLP_NPARAMS floats): W1[128][64], b1[128], W2[128][128], b2[128],
+ * W3[128], b3. */
+#define PAF_MLP_NPARAMS 24961
+paf_status paf_mlp_set_params(paf_ctx* ctx, const float* params /* [host] */);
+paf_status paf_mlp_get_params(paf_ctx* ctx, float* params /* [host] */);
+/* Predictions for n feature rows [device] -> out [device] fp32. */
+paf_status paf_mlp_forward(paf_ctx* ctx, const float* features, uint64_t n, float* out, void* stream);
+/* One training step on a minibatch: forward, MSE loss against targets,
+ * backward, and an Adam update (lr, beta1 0.9, beta2 0.999, eps 1e-8) of
+ * the master weights, then bf16 re-rounding.  features [device] [n][64],
+ * targets [device] fp32 [n], n <= 65536.  If grads != NULL [device,
+ * PAF_MLP_NPARAMS floats] the gradients are copied there; if loss != NULL
+ * [device] the mean loss is stored there.  If lr == 0 the weights are left
+ * unchanged (gradient only). */
+paf_status paf_mlp_train_step(paf_ctx* ctx, const float* features, const float* targets, uint64_t n,
+                              float lr, float* grads, float* loss, void* stream);
+
+/* Bucketing: bucket(p) = min(15, floor(16 * key(p) / key_max)) of a cost key
+ * computed from the prediction, the pair's length and threshold; writes a
+ * permutation of 0..n-1 grouped by bucket, stable within a bucket
+ * (perm [device] uint32 [n]) and the 16 bucket sizes (hist [device] uint32
+ * [16]). `pred` [device] fp32 [n]. */
+paf_status paf_bucket(paf_ctx* ctx, const paf_batch* batch, const float* pred, uint32_t* perm,
+                      uint32_t* hist, void* stream);
+
+/* The learned pipeline end to end: features -> model -> buckets -> persistent
+ * filter over the bucketed order -> decisions written at each pair's original
+ * index.  Decisions are identical to paf_filter's; only the order of work
+ * changes.  Needs a model (PAF_ERR_STATE otherwise).  Workspace is held by
+ * the context and grows to the largest batch seen. */
+paf_status paf_filter_bucketed(paf_ctx* ctx, const paf_batch* batch, uint32_t filters,
+                               const paf_out* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAF_H */

@@ -1,0 +1,326 @@
+"""paper_1910_03936_amd: MI355X-native pre-alignment filtering (SneakySnake,
+GateKeeper, Shouji) after Alser's thesis (arXiv 1910.03936).
+
+This module is a thin ctypes binding over libpaf.so (include/paf.h): it only
+marshals PyTorch device tensors and streams into the C ABI.  Every step of the
+filter runs in the library's HIP kernels; there is no CPU fallback, and
+importing the binding fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpaf.so")
+
+SNEAKYSNAKE, GATEKEEPER, SHOUJI = 1, 2, 4
+ALL_FILTERS = SNEAKYSNAKE | GATEKEEPER | SHOUJI
+MAX_LEN, MAX_E = 512, 31
+MLP_NPARAMS = 24961
+
+STATUS = {0: "PAF_OK", 1: "PAF_ERR_ARG", 2: "PAF_ERR_RANGE", 3: "PAF_ERR_DEVICE",
+          4: "PAF_ERR_NOMEM", 5: "PAF_ERR_STATE"}
+
+# Every symbol declared in include/paf.h.
+EXPORTS = ("paf_create", "paf_destroy", "paf_last_error", "paf_check", "paf_pack", "paf_pack_host",
+           "paf_filter", "paf_filter_persistent", "paf_autotune", "paf_set_layout", "paf_features",
+           "paf_mlp_set_params", "paf_mlp_get_params", "paf_mlp_forward", "paf_mlp_train_step",
+           "paf_bucket", "paf_filter_bucketed")
+
+
+class PafError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Batch(ctypes.Structure):
+    _fields_ = [("reads", ctypes.c_void_p), ("refs", ctypes.c_void_p),
+                ("word_offset", ctypes.c_void_p), ("stride_words", ctypes.c_uint32),
+                ("len", ctypes.c_void_p), ("uniform_len", ctypes.c_uint16),
+                ("E", ctypes.c_void_p), ("uniform_E", ctypes.c_uint8),
+                ("max_len", ctypes.c_uint16), ("max_E", ctypes.c_uint8),
+                ("n_pairs", ctypes.c_uint64)]
+
+
+class _Out(ctypes.Structure):
+    _fields_ = [("accept_bits", ctypes.c_void_p * 3), ("count", ctypes.c_void_p * 3)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("lanes_per_pair", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
+                ("blocks_per_cu", ctypes.c_uint32), ("tiles_per_grab", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpaf.so; raises if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libpaf.so not built at {path}: run __graft_entry__.build() "
+                          f"or python -m paper_1910_03936_amd.build")
+    lib = ctypes.CDLL(path)
+    P, U32, U64, I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    sig = {
+        "paf_create": ([ctypes.POINTER(P), I]),
+        "paf_destroy": ([P]),
+        "paf_check": ([P, P]),
+        "paf_pack": ([P, P, U32, P, ctypes.c_uint16, P, U32, U64, P, P]),
+        "paf_pack_host": ([P, U32, P, ctypes.c_uint16, P, U32, U64, P, I]),
+        "paf_filter": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
+        "paf_filter_persistent": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
+        "paf_autotune": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P,
+                          ctypes.POINTER(Layout), ctypes.POINTER(ctypes.c_float),
+                          ctypes.POINTER(ctypes.c_float)]),
+        "paf_set_layout": ([P, ctypes.POINTER(Layout)]),
+        "paf_features": ([P, ctypes.POINTER(_Batch), P, P]),
+        "paf_mlp_set_params": ([P, P]),
+        "paf_mlp_get_params": ([P, P]),
+        "paf_mlp_forward": ([P, P, U64, P, P]),
+        "paf_mlp_train_step": ([P, P, P, U64, ctypes.c_float, P, P, P]),
+        "paf_bucket": ([P, ctypes.POINTER(_Batch), P, P, P, P]),
+        "paf_filter_bucketed": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.paf_last_error.argtypes = []
+    lib.paf_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        msg = _lib.paf_last_error().decode(errors="replace")
+        raise PafError(status, msg)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def words_for(m: int) -> int:
+    return (m + 31) // 32
+
+
+@dataclass
+class Batch:
+    """Device-resident packed pairs, in the layout of paf_batch."""
+    reads: torch.Tensor                      # int64 words (uint64 bit patterns)
+    refs: torch.Tensor
+    n_pairs: int
+    stride_words: int = 0
+    word_offset: torch.Tensor | None = None  # int64 [n]
+    len: torch.Tensor | None = None          # int16 [n] (uint16 values)
+    E: torch.Tensor | None = None            # uint8 [n]
+    uniform_len: int = 0
+    uniform_E: int = 0
+    max_len: int = 0
+    max_E: int = 0
+
+    def c(self) -> _Batch:
+        b = _Batch()
+        b.reads = self.reads.data_ptr()
+        b.refs = self.refs.data_ptr()
+        b.word_offset = None if self.word_offset is None else self.word_offset.data_ptr()
+        b.stride_words = self.stride_words
+        b.len = None if self.len is None else self.len.data_ptr()
+        b.uniform_len = self.uniform_len
+        b.E = None if self.E is None else self.E.data_ptr()
+        b.uniform_E = self.uniform_E
+        b.max_len = self.max_len or self.uniform_len
+        b.max_E = self.max_E or self.uniform_E
+        b.n_pairs = self.n_pairs
+        return b
+
+    @property
+    def device(self):
+        return self.reads.device
+
+
+class Context:
+    """Owns a paf_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(self.lib.paf_create(ctypes.byref(h), device))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(self.lib.paf_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, stream=None):
+        _check(self.lib.paf_check(self.h, _stream(stream)))
+
+    # -- a1: encode -------------------------------------------------------
+    def pack(self, codes: torch.Tensor, lens: torch.Tensor | None = None, uniform_len: int = 0,
+             word_offset: torch.Tensor | None = None, stride_words: int = 0, total_words: int = 0,
+             stream=None) -> torch.Tensor:
+        """codes: uint8 [n, code_stride] device tensor -> int64 words."""
+        n, cs = codes.shape
+        if word_offset is None:
+            stride_words = stride_words or words_for(uniform_len or cs)
+            total_words = n * stride_words
+        words = torch.zeros(max(total_words, 1), dtype=torch.int64, device=codes.device)
+        _check(self.lib.paf_pack(self.h, _ptr(codes), cs, _ptr(lens), uniform_len, _ptr(word_offset),
+                                 stride_words, n, _ptr(words), _stream(stream)))
+        return words
+
+    def pack_pairs(self, reads_u8: torch.Tensor, refs_u8: torch.Tensor, lens=None, Es=None,
+                   uniform_len: int = 0, uniform_E: int = 0, max_len: int = 0, max_E: int = 0,
+                   offsets: bool = False, stream=None) -> Batch:
+        """Pack a batch of uint8 pairs (device tensors [n, stride]) into a Batch.
+        offsets=True packs per-pair lengths compactly with word offsets."""
+        n, cs = reads_u8.shape
+        dev = reads_u8.device
+        if lens is not None and offsets:
+            w = (lens.to(torch.int64) + 31) // 32
+            off = torch.zeros(n, dtype=torch.int64, device=dev)
+            off[1:] = torch.cumsum(w, 0)[:-1]
+            total = int(w.sum().item())
+            rd = self.pack(reads_u8, lens, 0, off, 0, total, stream)
+            rf = self.pack(refs_u8, lens, 0, off, 0, total, stream)
+            return Batch(rd, rf, n, 0, off, lens, Es, 0, uniform_E, max_len or cs, max_E or uniform_E)
+        stride = words_for(max_len or uniform_len or cs)
+        rd = self.pack(reads_u8, lens, uniform_len, None, stride, 0, stream)
+        rf = self.pack(refs_u8, lens, uniform_len, None, stride, 0, stream)
+        return Batch(rd, rf, n, stride, None, lens, Es, uniform_len, uniform_E,
+                     max_len or uniform_len or cs, max_E or uniform_E)
+
+    # -- a2..a7: filter ---------------------------------------------------
+    def alloc_out(self, n: int, filters: int, device) -> dict:
+        out = {}
+        for f in range(3):
+            if filters & (1 << f):
+                out[1 << f] = (torch.zeros((n + 31) // 32, dtype=torch.int32, device=device),
+                               torch.zeros(n, dtype=torch.int16, device=device))
+        return out
+
+    @staticmethod
+    def _out(out: dict) -> _Out:
+        o = _Out()
+        for f in range(3):
+            if (1 << f) in out:
+                a, c = out[1 << f]
+                o.accept_bits[f] = a.data_ptr()
+                o.count[f] = c.data_ptr()
+        return o
+
+    def filter(self, batch: Batch, filters: int = SNEAKYSNAKE, out: dict | None = None,
+               stream=None) -> dict:
+        out = out or self.alloc_out(batch.n_pairs, filters, batch.device)
+        cb, co = batch.c(), self._out(out)
+        _check(self.lib.paf_filter(self.h, ctypes.byref(cb), filters, ctypes.byref(co), _stream(stream)))
+        return out
+
+    def filter_persistent(self, batch: Batch, filters: int = SNEAKYSNAKE, out: dict | None = None,
+                          stream=None) -> dict:
+        out = out or self.alloc_out(batch.n_pairs, filters, batch.device)
+        cb, co = batch.c(), self._out(out)
+        _check(self.lib.paf_filter_persistent(self.h, ctypes.byref(cb), filters, ctypes.byref(co),
+                                              _stream(stream)))
+        return out
+
+    def autotune(self, batch: Batch, filters: int = SNEAKYSNAKE, stream=None):
+        out = self.alloc_out(batch.n_pairs, filters, batch.device)
+        cb, co = batch.c(), self._out(out)
+        lay = Layout()
+        best, dflt = ctypes.c_float(), ctypes.c_float()
+        _check(self.lib.paf_autotune(self.h, ctypes.byref(cb), filters, ctypes.byref(co), _stream(stream),
+                                     ctypes.byref(lay), ctypes.byref(best), ctypes.byref(dflt)))
+        return lay.as_dict(), best.value, dflt.value
+
+    def set_layout(self, layout: dict | None):
+        if layout is None:
+            _check(self.lib.paf_set_layout(self.h, None))
+        else:
+            lay = Layout(**layout)
+            _check(self.lib.paf_set_layout(self.h, ctypes.byref(lay)))
+
+    # -- a9/a10: cost model ----------------------------------------------
+    def features(self, batch: Batch, stream=None) -> torch.Tensor:
+        f = torch.empty((batch.n_pairs, 64), dtype=torch.float32, device=batch.device)
+        cb = batch.c()
+        _check(self.lib.paf_features(self.h, ctypes.byref(cb), _ptr(f), _stream(stream)))
+        return f
+
+    def mlp_set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        assert p.shape == (MLP_NPARAMS,)
+        _check(self.lib.paf_mlp_set_params(self.h, p.ctypes.data_as(ctypes.c_void_p)))
+
+    def mlp_get_params(self):
+        import numpy as np
+        p = np.zeros(MLP_NPARAMS, np.float32)
+        _check(self.lib.paf_mlp_get_params(self.h, p.ctypes.data_as(ctypes.c_void_p)))
+        return p
+
+    def mlp_forward(self, feats: torch.Tensor, stream=None) -> torch.Tensor:
+        out = torch.empty(feats.shape[0], dtype=torch.float32, device=feats.device)
+        _check(self.lib.paf_mlp_forward(self.h, _ptr(feats), feats.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def mlp_train_step(self, feats: torch.Tensor, targets: torch.Tensor, lr: float,
+                       want_grads: bool = False, stream=None):
+        grads = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=feats.device) if want_grads else None
+        loss = torch.empty(1, dtype=torch.float32, device=feats.device)
+        _check(self.lib.paf_mlp_train_step(self.h, _ptr(feats), _ptr(targets), feats.shape[0],
+                                           ctypes.c_float(lr), _ptr(grads), _ptr(loss), _stream(stream)))
+        return loss, grads
+
+    def bucket(self, batch: Batch, pred: torch.Tensor, stream=None):
+        perm = torch.empty(batch.n_pairs, dtype=torch.int32, device=batch.device)
+        hist = torch.empty(16, dtype=torch.int32, device=batch.device)
+        cb = batch.c()
+        _check(self.lib.paf_bucket(self.h, ctypes.byref(cb), _ptr(pred), _ptr(perm), _ptr(hist),
+                                   _stream(stream)))
+        return perm, hist
+
+    def filter_bucketed(self, batch: Batch, filters: int = SNEAKYSNAKE, out: dict | None = None,
+                        stream=None) -> dict:
+        out = out or self.alloc_out(batch.n_pairs, filters, batch.device)
+        cb, co = batch.c(), self._out(out)
+        _check(self.lib.paf_filter_bucketed(self.h, ctypes.byref(cb), filters, ctypes.byref(co),
+                                            _stream(stream)))
+        return out
+
+
+def accept_bits_to_bool(bits: torch.Tensor, n: int) -> torch.Tensor:
+    """Unpack accept-bit words (bit p%32 of word p/32) into a bool tensor [n]."""
+    b = bits.to(torch.int64) & 0xFFFFFFFF
+    shifts = torch.arange(32, device=bits.device, dtype=torch.int64)
+    return ((b[:, None] >> shifts[None, :]) & 1).reshape(-1)[:n].bool()
+
+
+def counts_u16(c: torch.Tensor) -> torch.Tensor:
+    """int16 storage of uint16 counts -> int32 values."""
+    return c.to(torch.int32) & 0xFFFF

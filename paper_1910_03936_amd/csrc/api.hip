@@ -1,0 +1,452 @@
+// Host side of libpaf: the C ABI declared in include/paf.h.
+#include <string.h>
+
+#include <algorithm>
+#include <thread>
+#include <vector>
+
+#include "paf_internal.h"
+
+using namespace paf;
+
+namespace {
+
+thread_local std::string g_err;
+
+paf_status fail(paf_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+paf_status hip_fail(hipError_t e, const char* what) {
+    return fail(PAF_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define PAF_HIP(call, what)                          \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+uint32_t words_for(uint32_t m) { return (m + 31u) / 32u; }
+
+// Host-side checks of a batch; fills the launch-invariant part of FilterParams.
+paf_status check_batch(const paf_ctx* ctx, const paf_batch* b, uint32_t filters, FilterParams& p) {
+    if (!ctx) return fail(PAF_ERR_ARG, "ctx is NULL");
+    if (!b) return fail(PAF_ERR_ARG, "batch is NULL");
+    if (!b->reads || !b->refs) return fail(PAF_ERR_ARG, "batch reads/refs is NULL");
+    if (b->n_pairs == 0) return fail(PAF_ERR_ARG, "batch has no pairs");
+    if (b->n_pairs > (uint64_t)UINT32_MAX * 64ull)
+        return fail(PAF_ERR_RANGE, "batch has too many pairs (max 2^32 tiles of 64)");
+    if (filters == 0 || filters > 7u) return fail(PAF_ERR_ARG, "filters must be a nonzero mask of PAF_* bits");
+    uint32_t max_len = b->max_len;
+    uint32_t max_E = b->max_E;
+    if (!b->len) {
+        if (b->uniform_len < 1 || b->uniform_len > PAF_MAX_LEN)
+            return fail(PAF_ERR_RANGE, "uniform_len outside [1, PAF_MAX_LEN]");
+        if (max_len == 0) max_len = b->uniform_len;
+        if (b->uniform_len > max_len) return fail(PAF_ERR_RANGE, "uniform_len exceeds max_len");
+    }
+    if (max_len < 1 || max_len > PAF_MAX_LEN) return fail(PAF_ERR_RANGE, "max_len outside [1, PAF_MAX_LEN]");
+    if (!b->E) {
+        if (b->uniform_E > PAF_MAX_E) return fail(PAF_ERR_RANGE, "uniform_E exceeds PAF_MAX_E");
+        if (b->uniform_E > max_E) max_E = b->uniform_E;
+    }
+    if (max_E > PAF_MAX_E) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
+    const uint32_t wmax = words_for(max_len);
+    if (!b->word_offset && b->stride_words < wmax)
+        return fail(PAF_ERR_ARG, "stride_words is smaller than ceil(max_len / 32)");
+    memset(&p, 0, sizeof(p));
+    p.reads = b->reads;
+    p.refs = b->refs;
+    p.word_offset = b->word_offset;
+    p.stride_words = b->stride_words;
+    p.len = b->len;
+    p.uniform_len = b->len ? 0u : b->uniform_len;
+    p.E = b->E;
+    p.uniform_E = b->E ? 0u : b->uniform_E;
+    p.n_pairs = b->n_pairs;
+    p.n_tiles = (uint32_t)((b->n_pairs + 63) / 64);
+    p.wmax = wmax;
+    p.max_len = max_len;
+    p.max_E = max_E;
+    p.filters = filters;
+    p.err = ctx->d_err;
+    p.grab = 1;
+    return PAF_OK;
+}
+
+paf_status check_out(const paf_out* out, uint32_t filters) {
+    if (!out) return fail(PAF_ERR_ARG, "out is NULL");
+    for (int f = 0; f < 3; ++f)
+        if ((filters >> f) & 1u)
+            if (!out->accept_bits[f] || !out->count[f])
+                return fail(PAF_ERR_ARG, "a requested filter has a NULL output pointer");
+    return PAF_OK;
+}
+
+Engine engine_for(uint32_t filters) {
+    return filters == PAF_SNEAKYSNAKE ? Engine::Snake : Engine::Whole;
+}
+
+// Block-size limit of each engine (its launch bound).
+uint32_t max_waves(Engine e) { return e == Engine::Snake ? 8u : 4u; }
+
+hipError_t allow_lds(const void* k, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// Default layout of the persistent launch.
+paf_layout default_layout() {
+    paf_layout l;
+    l.lanes_per_pair = 1;
+    l.waves_per_block = 4;
+    l.blocks_per_cu = 4;
+    l.tiles_per_grab = 1;
+    return l;
+}
+
+bool layout_ok(const paf_layout& l) {
+    return l.lanes_per_pair == 1 &&
+           (l.waves_per_block == 1 || l.waves_per_block == 2 || l.waves_per_block == 4 ||
+            l.waves_per_block == 8) &&
+           l.blocks_per_cu >= 1 && l.blocks_per_cu <= 64 && l.tiles_per_grab >= 1 &&
+           l.tiles_per_grab <= 64;
+}
+
+// Largest resident block count per CU for this kernel and LDS size.
+int resident_blocks(const void* k, uint32_t waves, size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64 * waves, lds) != hipSuccess) return 1;
+    return std::max(1, nb);
+}
+
+uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+    return h;
+}
+
+// Launch the persistent filter through a cached HIP graph (queue reset by a
+// fill kernel, then the kernel).  The graph is captured on a private stream
+// and launched on `stream`.
+paf_status run_persistent(paf_ctx* ctx, FilterParams p, Engine eng, int emax, const paf_layout& L,
+                          hipStream_t stream, bool use_graph) {
+    const bool general = true;
+    const void* k = filter_kernel_ptr(eng, general, emax);
+    if (!k) return fail(PAF_ERR_RANGE, "no kernel for this threshold");
+    if (L.waves_per_block > max_waves(eng)) return fail(PAF_ERR_ARG, "too many waves per block for this engine");
+    LaunchShape sh;
+    sh.waves_per_block = L.waves_per_block;
+    sh.lds_bytes = filter_lds_bytes(L.waves_per_block, p.wmax);
+    if (sh.lds_bytes > 160 * 1024) return fail(PAF_ERR_RANGE, "layout needs more LDS than a CU has");
+    PAF_HIP(allow_lds(k, sh.lds_bytes), "hipFuncSetAttribute");
+    const int nb = std::min<int>((int)L.blocks_per_cu, resident_blocks(k, L.waves_per_block, sh.lds_bytes));
+    const uint64_t want = (uint64_t)ctx->num_cus * nb;
+    const uint64_t need = (p.n_tiles + L.waves_per_block - 1) / L.waves_per_block;
+    sh.blocks = (uint32_t)std::max<uint64_t>(1, std::min(want, need));
+    p.queue = ctx->d_queue;
+    p.grab = L.tiles_per_grab;
+    if (!use_graph) {
+        PAF_HIP(launch_fill_u32(ctx->d_queue, 0u, 1, stream), "queue reset");
+        PAF_HIP(launch_filter(p, eng, general, emax, sh, stream), "filter launch");
+        return PAF_OK;
+    }
+    paf_ctx::GraphKey key{0, 0, 0, 0};
+    const uint64_t* words = reinterpret_cast<const uint64_t*>(&p);
+    for (size_t i = 0; i < sizeof(p) / 8; ++i) key.a = mix(key.a, words[i]);
+    key.b = mix(mix((uint64_t)eng, (uint64_t)emax), (uint64_t)L.waves_per_block);
+    key.c = mix(mix(sh.blocks, sh.lds_bytes), L.tiles_per_grab);
+    key.d = p.n_pairs;
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        if (ctx->graphs.size() >= 64) {
+            for (auto& kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+            ctx->graphs.clear();
+        }
+        hipStream_t cap;
+        PAF_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate");
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e1 = launch_fill_u32(ctx->d_queue, 0u, 1, cap);
+            hipError_t e2 = launch_filter(p, eng, general, emax, sh, cap);
+            e = hipStreamEndCapture(cap, &g);
+            if (e == hipSuccess && (e1 != hipSuccess || e2 != hipSuccess)) e = e1 != hipSuccess ? e1 : e2;
+        }
+        hipGraphExec_t ex = nullptr;
+        if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (g) hipGraphDestroy(g);
+        hipStreamDestroy(cap);
+        if (e != hipSuccess) return hip_fail(e, "graph capture of the persistent filter");
+        it = ctx->graphs.emplace(key, ex).first;
+    }
+    PAF_HIP(hipGraphLaunch(it->second, stream), "hipGraphLaunch");
+    return PAF_OK;
+}
+
+paf_layout layout_for(paf_ctx* ctx, const FilterParams& p, int emax) {
+    if (ctx->layout_forced) return ctx->forced;
+    auto it = ctx->tuned.find(std::make_tuple((int)p.wmax, emax, p.filters));
+    if (it != ctx->tuned.end()) return it->second;
+    return default_layout();
+}
+
+void set_outputs(FilterParams& p, const paf_out* out) {
+    for (int f = 0; f < 3; ++f) {
+        p.acc[f] = ((p.filters >> f) & 1u) ? out->accept_bits[f] : nullptr;
+        p.cnt[f] = ((p.filters >> f) & 1u) ? out->count[f] : nullptr;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* paf_last_error(void) { return g_err.c_str(); }
+
+paf_status paf_create(paf_ctx** out, int device) {
+    if (!out) return fail(PAF_ERR_ARG, "ctx pointer is NULL");
+    *out = nullptr;
+    int n = 0;
+    PAF_HIP(hipGetDeviceCount(&n), "hipGetDeviceCount");
+    if (device < 0 || device >= n) return fail(PAF_ERR_ARG, "no such device");
+    PAF_HIP(hipSetDevice(device), "hipSetDevice");
+    paf_ctx* c = new (std::nothrow) paf_ctx();
+    if (!c) return fail(PAF_ERR_NOMEM, "host allocation failed");
+    c->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->num_cus = cus;
+    if (hipMalloc(&c->d_err, 2 * sizeof(uint32_t)) != hipSuccess) {
+        delete c;
+        return fail(PAF_ERR_NOMEM, "device allocation failed");
+    }
+    c->d_queue = c->d_err + 1;
+    if (hipMemset(c->d_err, 0, 2 * sizeof(uint32_t)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        hipFree(c->d_err);
+        delete c;
+        return fail(PAF_ERR_DEVICE, "device initialisation failed");
+    }
+    *out = c;
+    return PAF_OK;
+}
+
+paf_status paf_destroy(paf_ctx* ctx) {
+    if (!ctx) return fail(PAF_ERR_ARG, "ctx is NULL");
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    for (auto& kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+    hipFree(ctx->d_err);
+    if (ctx->mlp.master) {
+        hipFree(ctx->mlp.master);
+        hipFree(ctx->mlp.w16);
+        hipFree(ctx->mlp.adam_m);
+        hipFree(ctx->mlp.adam_v);
+        hipFree(ctx->mlp.grad);
+    }
+    if (ctx->mlp.act) hipFree(ctx->mlp.act);
+    hipFree(ctx->ws_feat);
+    hipFree(ctx->ws_pred);
+    hipFree(ctx->ws_perm);
+    hipFree(ctx->ws_hist);
+    hipFree(ctx->ws_bucket);
+    for (int f = 0; f < 3; ++f) hipFree(ctx->ws_cnt[f]);
+    delete ctx;
+    return PAF_OK;
+}
+
+paf_status paf_check(paf_ctx* ctx, void* stream) {
+    if (!ctx) return fail(PAF_ERR_ARG, "ctx is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t flag = 0;
+    PAF_HIP(hipMemcpyAsync(&flag, ctx->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    PAF_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (flag) {
+        PAF_HIP(launch_fill_u32(ctx->d_err, 0u, 1, s), "flag reset");
+        PAF_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+        return fail(PAF_ERR_RANGE, "a pair had a length, threshold or base code outside the batch's bounds");
+    }
+    return PAF_OK;
+}
+
+paf_status paf_pack(paf_ctx* ctx, const uint8_t* codes, uint32_t code_stride, const uint16_t* len,
+                    uint16_t uniform_len, const uint64_t* word_offset, uint32_t stride_words,
+                    uint64_t n, uint64_t* words, void* stream) {
+    if (!ctx) return fail(PAF_ERR_ARG, "ctx is NULL");
+    if (!codes || !words) return fail(PAF_ERR_ARG, "codes/words is NULL");
+    if (n == 0) return fail(PAF_ERR_ARG, "n is zero");
+    if (!len && (uniform_len < 1 || uniform_len > PAF_MAX_LEN))
+        return fail(PAF_ERR_RANGE, "uniform_len outside [1, PAF_MAX_LEN]");
+    const uint32_t maxm = len ? PAF_MAX_LEN : uniform_len;
+    if (code_stride < (len ? 1u : (uint32_t)uniform_len)) return fail(PAF_ERR_ARG, "code_stride too small");
+    if (!word_offset && stride_words < words_for(maxm) && !len)
+        return fail(PAF_ERR_ARG, "stride_words too small");
+    // With per-pair lengths every length must fit the stride; lengths are
+    // device data, so the kernel clips with the threads it launches.
+    const uint32_t wmax = len ? std::min<uint32_t>(words_for(PAF_MAX_LEN),
+                                                   word_offset ? words_for(PAF_MAX_LEN) : stride_words)
+                              : words_for(uniform_len);
+    PAF_HIP(launch_pack(codes, code_stride, len, uniform_len, word_offset, stride_words, n, wmax, words,
+                        ctx->d_err, (hipStream_t)stream),
+            "pack launch");
+    return PAF_OK;
+}
+
+paf_status paf_pack_host(const uint8_t* codes, uint32_t code_stride, const uint16_t* len,
+                         uint16_t uniform_len, const uint64_t* word_offset, uint32_t stride_words,
+                         uint64_t n, uint64_t* words, int threads) {
+    if (!codes || !words) return fail(PAF_ERR_ARG, "codes/words is NULL");
+    if (n == 0) return fail(PAF_ERR_ARG, "n is zero");
+    if (!len && (uniform_len < 1 || uniform_len > PAF_MAX_LEN))
+        return fail(PAF_ERR_RANGE, "uniform_len outside [1, PAF_MAX_LEN]");
+    if (threads <= 0) threads = (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+    std::vector<int> bad((size_t)threads, 0);
+    auto work = [&](int t) {
+        const uint64_t a = n * (uint64_t)t / threads, b = n * (uint64_t)(t + 1) / threads;
+        for (uint64_t p = a; p < b; ++p) {
+            const uint32_t m = len ? len[p] : uniform_len;
+            if (m < 1 || m > PAF_MAX_LEN || m > code_stride ||
+                (!word_offset && words_for(m) > stride_words)) {
+                bad[t] = 2;
+                continue;
+            }
+            const uint8_t* row = codes + p * (uint64_t)code_stride;
+            uint64_t* dst = words + (word_offset ? word_offset[p] : p * (uint64_t)stride_words);
+            for (uint32_t k = 0; k < words_for(m); ++k) {
+                uint32_t lo = 0, hi = 0;
+                const uint32_t cnt = std::min(32u, m - 32u * k);
+                for (uint32_t j = 0; j < cnt; ++j) {
+                    const uint32_t v = row[32u * k + j];
+                    if (v > 3u) bad[t] = 1;
+                    lo |= (v & 1u) << j;
+                    hi |= ((v >> 1) & 1u) << j;
+                }
+                dst[k] = ((uint64_t)hi << 32) | lo;
+            }
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < threads; ++t) pool.emplace_back(work, t);
+    work(0);
+    for (auto& th : pool) th.join();
+    for (int v : bad)
+        if (v) return fail(PAF_ERR_RANGE, v == 1 ? "base code above 3" : "pair length outside range or stride");
+    return PAF_OK;
+}
+
+paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, const paf_out* out,
+                      void* stream) {
+    FilterParams p;
+    paf_status st = check_batch(ctx, batch, filters, p);
+    if (st != PAF_OK) return st;
+    if ((st = check_out(out, filters)) != PAF_OK) return st;
+    const int emax = emax_bucket((int)p.max_E);
+    if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
+    set_outputs(p, out);
+    const bool general = batch->len || batch->E || batch->word_offset;
+    const Engine eng = engine_for(filters);
+    LaunchShape sh;
+    sh.waves_per_block = p.wmax > 8 ? 2 : 4;
+    sh.lds_bytes = filter_lds_bytes(sh.waves_per_block, p.wmax);
+    sh.blocks = (uint32_t)((p.n_tiles + sh.waves_per_block - 1) / sh.waves_per_block);
+    PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    PAF_HIP(allow_lds(filter_kernel_ptr(eng, general, emax), sh.lds_bytes), "hipFuncSetAttribute");
+    PAF_HIP(launch_filter(p, eng, general, emax, sh, (hipStream_t)stream), "filter launch");
+    return PAF_OK;
+}
+
+paf_status paf_filter_persistent(paf_ctx* ctx, const paf_batch* batch, uint32_t filters,
+                                 const paf_out* out, void* stream) {
+    FilterParams p;
+    paf_status st = check_batch(ctx, batch, filters, p);
+    if (st != PAF_OK) return st;
+    if ((st = check_out(out, filters)) != PAF_OK) return st;
+    const int emax = emax_bucket((int)p.max_E);
+    if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
+    set_outputs(p, out);
+    PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    const paf_layout L = layout_for(ctx, p, emax);
+    return run_persistent(ctx, p, engine_for(filters), emax, L, (hipStream_t)stream, true);
+}
+
+paf_status paf_set_layout(paf_ctx* ctx, const paf_layout* layout) {
+    if (!ctx) return fail(PAF_ERR_ARG, "ctx is NULL");
+    if (!layout) {
+        ctx->layout_forced = false;
+        return PAF_OK;
+    }
+    if (!layout_ok(*layout)) return fail(PAF_ERR_ARG, "unsupported layout");
+    ctx->forced = *layout;
+    ctx->layout_forced = true;
+    return PAF_OK;
+}
+
+paf_status paf_autotune(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, const paf_out* out,
+                        void* stream, paf_layout* chosen, float* best_ms, float* default_ms) {
+    FilterParams p;
+    paf_status st = check_batch(ctx, batch, filters, p);
+    if (st != PAF_OK) return st;
+    if ((st = check_out(out, filters)) != PAF_OK) return st;
+    const int emax = emax_bucket((int)p.max_E);
+    if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
+    set_outputs(p, out);
+    PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const Engine eng = engine_for(filters);
+    std::vector<paf_layout> cands;
+    for (uint32_t wpb : {1u, 2u, 4u, 8u})
+        for (uint32_t bpc : {1u, 2u, 4u, 8u, 16u})
+            for (uint32_t grab : {1u, 4u}) {
+                paf_layout l{1u, wpb, bpc, grab};
+                if (filter_lds_bytes(wpb, p.wmax) * bpc > 160 * 1024) continue;
+                if (wpb * bpc > 32 || wpb > max_waves(eng)) continue;
+                cands.push_back(l);
+            }
+    hipEvent_t e0, e1;
+    PAF_HIP(hipEventCreate(&e0), "hipEventCreate");
+    PAF_HIP(hipEventCreate(&e1), "hipEventCreate");
+    auto time_layout = [&](const paf_layout& l, float& ms) -> paf_status {
+        paf_status r = run_persistent(ctx, p, eng, emax, l, s, false);  // warm-up
+        if (r != PAF_OK) return r;
+        float best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            PAF_HIP(hipEventRecord(e0, s), "hipEventRecord");
+            r = run_persistent(ctx, p, eng, emax, l, s, false);
+            if (r != PAF_OK) return r;
+            PAF_HIP(hipEventRecord(e1, s), "hipEventRecord");
+            PAF_HIP(hipEventSynchronize(e1), "hipEventSynchronize");
+            float t = 0;
+            PAF_HIP(hipEventElapsedTime(&t, e0, e1), "hipEventElapsedTime");
+            best = std::min(best, t);
+        }
+        ms = best;
+        return PAF_OK;
+    };
+    paf_layout best_l = default_layout();
+    float best_t = 1e30f, def_t = 0;
+    st = time_layout(default_layout(), def_t);
+    if (st == PAF_OK) {
+        best_t = def_t;
+        for (const auto& l : cands) {
+            float t = 0;
+            st = time_layout(l, t);
+            if (st != PAF_OK) break;
+            if (t < best_t) {
+                best_t = t;
+                best_l = l;
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != PAF_OK) return st;
+    ctx->tuned[std::make_tuple((int)p.wmax, emax, p.filters)] = best_l;
+    if (chosen) *chosen = best_l;
+    if (best_ms) *best_ms = best_t;
+    if (default_ms) *default_ms = def_t;
+    return PAF_OK;
+}
+
+}  // extern "C"
