@@ -286,26 +286,41 @@ template <int EMAX, bool GENERAL>
 __device__ void snake_tile(const FilterParams& P, uint64_t tile, int lane, uint64_t* rdL,
                            uint64_t* rfL) {
     constexpr int D = 2 * EMAX + 1;
-    using DT = typename DeadMask<EMAX>::T;
     uint64_t off;
     const PairSlot ps = load_slot<GENERAL>(P, tile, lane, off);
     stage_tile<GENERAL>(P, tile, lane, ps, off, rdL, rfL);
 
-    Snake z{0u, 0u, ps.valid, false, 0u};
-    bool cont = false;
-    DT dead = 0;
     const uint32_t m = ps.m, E = ps.E;
     // Diagonals beyond the pair's own threshold are fully blocked.
     const bool mask_E = GENERAL ? (P.E != nullptr || P.uniform_E < (uint32_t)EMAX)
                                 : (P.uniform_E < (uint32_t)EMAX);
+    uint32_t c = 0, e = 0;
+    bool act = ps.valid, acc = false;
+    // A lane whose deepest pipe ran past the end of the previous window enters
+    // the next one still inside that pipe: only the diagonals that were clear
+    // up to the window's end (from its probe at shift s_prev) may carry it on.
+    // Their complement is folded into bit 0 of the new window's map words;
+    // bit 0 is only ever read by that first probe (after it, s >= 1).
+    uint32_t cont = 0, s_prev = 0;
+    uint32_t M[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) M[i] = 0u;
 
-    for (uint32_t w = 0; wave_any(z.act); ++w) {
-        uint32_t M[D];
-        if (z.act) {
+    for (uint32_t w = 0; wave_any(act); ++w) {
+        if (act) {
             const WindowWords q = window_words(rdL, rfL, lane, (int)w, P.wmax, (int)m);
             // Vacant cells only occur in the first window and near the end.
-            const bool boundary = wave_any(z.act && (w == 0 || 32u * (w + 2) > m));
-            build_snake_map<EMAX>(q, boundary, M);
+            const bool boundary = wave_any(w == 0 || 32u * (w + 2) > m);
+            const bool any_cont = wave_any(cont != 0u);
+            uint32_t T[D];
+            build_snake_map<EMAX>(q, boundary, T);
+            if (any_cont) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) M[i] = T[i] | min(M[i] >> s_prev, cont);
+            } else {
+#pragma unroll
+                for (int i = 0; i < D; ++i) M[i] = T[i];
+            }
             if (mask_E) {
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
@@ -313,16 +328,43 @@ __device__ void snake_tile(const FilterParams& P, uint64_t tile, int lane, uint6
                     if ((uint32_t)(d < 0 ? -d : d) > E) M[i] = ~0u;
                 }
             }
-            snake_window<EMAX, DT>(z, M, w, m, E, cont, dead);
+            cont = 0u;
+            // Steps inside this window: probe every diagonal from column c,
+            // follow the deepest pipe, cross its obstacle (one edit, one
+            // column) or finish.
+            const uint32_t w0 = 32u * w, wend = w0 + 32u;
+            bool inw = c < wend;
+            while (inw) {
+                const uint32_t s = c - w0;
+                uint32_t best = 0;
+#pragma unroll
+                for (int i = 0; i < D; ++i) best = max(best, ffbl(M[i] >> s));
+                const bool clear = best == 0xFFFFFFFFu;   // a pipe runs past the window
+                const uint32_t R = clear ? wend : c + best;
+                const bool reach = R >= m;                 // the pipe reaches the last column
+                const bool obst = !reach && !clear;
+                e += obst ? 1u : 0u;
+                c = reach ? c : (clear ? wend : R + 1u);
+                const bool rej = e > E;
+                const bool fin_acc = reach || (obst && !rej && c >= m);
+                acc = fin_acc;
+                if (clear && !reach) {
+                    cont = 1u;
+                    s_prev = s;
+                }
+                act = !(fin_acc || rej);
+                inw = act && c < wend;
+            }
         }
     }
+    const uint32_t cnt = e;  // e <= E for accepts, E + 1 for rejects
 
     // Outputs.
     if (GENERAL && P.perm) {
-        if (ps.in_batch) P.cnt[0][ps.id] = (uint16_t)(ps.valid ? z.cnt : 0u);
+        if (ps.in_batch) P.cnt[0][ps.id] = (uint16_t)(ps.valid ? cnt : 0u);
     } else {
-        const uint64_t bal = __ballot(ps.valid && z.acc);
-        if (ps.in_batch) P.cnt[0][ps.slot] = (uint16_t)(ps.valid ? z.cnt : 0u);
+        const uint64_t bal = __ballot(ps.valid && acc);
+        if (ps.in_batch) P.cnt[0][ps.slot] = (uint16_t)(ps.valid ? cnt : 0u);
         if (lane == 0) {
             P.acc[0][2 * tile] = (uint32_t)bal;
             if (tile * 64 + 32 < P.n_pairs) P.acc[0][2 * tile + 1] = (uint32_t)(bal >> 32);
