@@ -176,11 +176,31 @@ paf_status paf_mlp_forward(paf_ctx* ctx, const float* features, uint64_t n, floa
 paf_status paf_mlp_train_step(paf_ctx* ctx, const float* features, const float* targets, uint64_t n,
                               float lr, float* grads, float* loss, void* stream);
 
-/* Bucketing: bucket(p) = min(15, floor(16 * key(p) / key_max)) of a cost key
- * computed from the prediction, the pair's length and threshold; writes a
- * permutation of 0..n-1 grouped by bucket, stable within a bucket
+/* Predictions of the cost model for every pair of a batch, computed by the
+ * fused kernel the bucketed filter uses (features -> model on the matrix
+ * cores).  pred [device] fp32 [n]; pairs that fail the device-side checks
+ * get 0.  Needs a model (PAF_ERR_STATE otherwise). */
+paf_status paf_mlp_predict(paf_ctx* ctx, const paf_batch* batch, float* pred, void* stream);
+
+/* Trains the model on n labelled feature rows for `epochs` passes over
+ * consecutive minibatches of `batch` rows (the caller shuffles the rows),
+ * with paf_mlp_train_step's Adam update.  features [device] fp32 [n][64],
+ * labels [device] uint16 [n] (the target counts).  epoch_loss [host,
+ * `epochs` floats] receives each epoch's mean minibatch loss if not NULL.
+ * Synchronizes `stream` before returning. */
+paf_status paf_mlp_train(paf_ctx* ctx, const float* features, const uint16_t* labels, uint64_t n,
+                         uint32_t epochs, uint32_t batch, float lr, float* epoch_loss, void* stream);
+
+/* Bucketing.  From a prediction y (the model's estimate of SneakySnake's
+ * obstacle count over the whole maze) and the pair's m and E, the number of
+ * 32-column windows the snake is expected to traverse at the pair's own
+ * threshold is estimated (it stops after E+1 obstacles, so it covers about
+ * m (E+1)/y columns when y > E+1, else all m), refined by the expected number
+ * of steps, and quantised to a level 0..15 against the longest pair the
+ * batch's bounds allow; bucket = 15 - level, so the longest work comes first.
+ * Writes a permutation of 0..n-1 grouped by bucket, stable within a bucket
  * (perm [device] uint32 [n]) and the 16 bucket sizes (hist [device] uint32
- * [16]). `pred` [device] fp32 [n]. */
+ * [16]).  pred [device] fp32 [n]. */
 paf_status paf_bucket(paf_ctx* ctx, const paf_batch* batch, const float* pred, uint32_t* perm,
                       uint32_t* hist, void* stream);
 

@@ -219,3 +219,17 @@ def encode(s: str) -> np.ndarray:
 
 def decode(codes) -> str:
     return "".join(BASES[int(c)] for c in codes)
+
+
+def init_mlp_params(seed: int = SEED_BASE + 17) -> np.ndarray:
+    """Seeded initial weights of the 64 -> 128 -> 128 -> 1 cost model (flat
+    fp32, layout W1[128][64], b1[128], W2[128][128], b2[128], W3[128], b3):
+    He-uniform weight matrices U(-sqrt(6 / fan_in), +sqrt(6 / fan_in)), zero
+    biases.  Random numbers only, so both sides take them as input."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for rows, fan_in in ((128, 64), (128, 128), (1, 128)):
+        a = np.sqrt(6.0 / fan_in)
+        parts.append(rng.uniform(-a, a, rows * fan_in))
+        parts.append(np.zeros(rows))
+    return np.concatenate(parts).astype(np.float32)

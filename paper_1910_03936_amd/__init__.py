@@ -29,7 +29,7 @@ STATUS = {0: "PAF_OK", 1: "PAF_ERR_ARG", 2: "PAF_ERR_RANGE", 3: "PAF_ERR_DEVICE"
 EXPORTS = ("paf_create", "paf_destroy", "paf_last_error", "paf_check", "paf_pack", "paf_pack_host",
            "paf_filter", "paf_filter_persistent", "paf_autotune", "paf_set_layout", "paf_features",
            "paf_mlp_set_params", "paf_mlp_get_params", "paf_mlp_forward", "paf_mlp_train_step",
-           "paf_bucket", "paf_filter_bucketed")
+           "paf_mlp_predict", "paf_mlp_train", "paf_bucket", "paf_filter_bucketed")
 
 
 class PafError(RuntimeError):
@@ -90,6 +90,8 @@ def load_library(path: str = LIB_PATH):
         "paf_mlp_forward": ([P, P, U64, P, P]),
         "paf_mlp_train_step": ([P, P, P, U64, ctypes.c_float, P, P, P]),
         "paf_bucket": ([P, ctypes.POINTER(_Batch), P, P, P, P]),
+        "paf_mlp_predict": ([P, ctypes.POINTER(_Batch), P, P]),
+        "paf_mlp_train": ([P, P, P, U64, U32, U32, ctypes.c_float, P, P]),
         "paf_filter_bucketed": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
     }
     for name, args in sig.items():
@@ -296,6 +298,22 @@ class Context:
         _check(self.lib.paf_mlp_train_step(self.h, _ptr(feats), _ptr(targets), feats.shape[0],
                                            ctypes.c_float(lr), _ptr(grads), _ptr(loss), _stream(stream)))
         return loss, grads
+
+    def mlp_predict(self, batch: Batch, stream=None) -> torch.Tensor:
+        """Fused features + model predictions for every pair of the batch."""
+        pred = torch.empty(batch.n_pairs, dtype=torch.float32, device=batch.device)
+        cb = batch.c()
+        _check(self.lib.paf_mlp_predict(self.h, ctypes.byref(cb), _ptr(pred), _stream(stream)))
+        return pred
+
+    def mlp_train(self, feats: torch.Tensor, labels: torch.Tensor, epochs: int, batch: int, lr: float,
+                  stream=None):
+        """Train on feature rows [n][64] fp32 and uint16 labels (int16 tensor)."""
+        import numpy as np
+        loss = np.zeros(epochs, np.float32)
+        _check(self.lib.paf_mlp_train(self.h, _ptr(feats), _ptr(labels), feats.shape[0], epochs, batch,
+                                      ctypes.c_float(lr), loss.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return loss
 
     def bucket(self, batch: Batch, pred: torch.Tensor, stream=None):
         perm = torch.empty(batch.n_pairs, dtype=torch.int32, device=batch.device)

@@ -10,9 +10,10 @@
 using namespace paf;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
+namespace paf {
 paf_status fail(paf_status st, const std::string& msg) {
     g_err = msg;
     return st;
@@ -21,14 +22,6 @@ paf_status fail(paf_status st, const std::string& msg) {
 paf_status hip_fail(hipError_t e, const char* what) {
     return fail(PAF_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
-
-#define PAF_HIP(call, what)                          \
-    do {                                             \
-        hipError_t e_ = (call);                      \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
-
-uint32_t words_for(uint32_t m) { return (m + 31u) / 32u; }
 
 // Host-side checks of a batch; fills the launch-invariant part of FilterParams.
 paf_status check_batch(const paf_ctx* ctx, const paf_batch* b, uint32_t filters, FilterParams& p) {
@@ -75,6 +68,10 @@ paf_status check_batch(const paf_ctx* ctx, const paf_batch* b, uint32_t filters,
     p.grab = 1;
     return PAF_OK;
 }
+
+}  // namespace paf
+
+namespace {
 
 paf_status check_out(const paf_out* out, uint32_t filters) {
     if (!out) return fail(PAF_ERR_ARG, "out is NULL");
@@ -127,6 +124,37 @@ uint64_t mix(uint64_t h, uint64_t v) {
     return h;
 }
 
+// Replays the graph cached under `key`, or captures `body` (which must only
+// enqueue work on the stream it is given) into a new graph first.
+template <typename F>
+paf_status run_graph(paf_ctx* ctx, const paf_ctx::GraphKey& key, hipStream_t stream, F&& body) {
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        if (ctx->graphs.size() >= 64) {
+            for (auto& kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+            ctx->graphs.clear();
+        }
+        hipStream_t cap;
+        PAF_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate");
+        hipGraph_t g = nullptr;
+        paf_status st = PAF_OK;
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            st = body(cap);
+            e = hipStreamEndCapture(cap, &g);
+        }
+        hipGraphExec_t ex = nullptr;
+        if (e == hipSuccess && st == PAF_OK) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (g) hipGraphDestroy(g);
+        hipStreamDestroy(cap);
+        if (st != PAF_OK) return st;
+        if (e != hipSuccess) return hip_fail(e, "graph capture");
+        it = ctx->graphs.emplace(key, ex).first;
+    }
+    PAF_HIP(hipGraphLaunch(it->second, stream), "hipGraphLaunch");
+    return PAF_OK;
+}
+
 // Launch the persistent filter through a cached HIP graph (queue reset by a
 // fill kernel, then the kernel).  The graph is captured on a private stream
 // and launched on `stream`.
@@ -158,30 +186,32 @@ paf_status run_persistent(paf_ctx* ctx, FilterParams p, Engine eng, int emax, co
     key.b = mix(mix((uint64_t)eng, (uint64_t)emax), (uint64_t)L.waves_per_block);
     key.c = mix(mix(sh.blocks, sh.lds_bytes), L.tiles_per_grab);
     key.d = p.n_pairs;
-    auto it = ctx->graphs.find(key);
-    if (it == ctx->graphs.end()) {
-        if (ctx->graphs.size() >= 64) {
-            for (auto& kv : ctx->graphs) hipGraphExecDestroy(kv.second);
-            ctx->graphs.clear();
-        }
-        hipStream_t cap;
-        PAF_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate");
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            hipError_t e1 = launch_fill_u32(ctx->d_queue, 0u, 1, cap);
-            hipError_t e2 = launch_filter(p, eng, general, emax, sh, cap);
-            e = hipStreamEndCapture(cap, &g);
-            if (e == hipSuccess && (e1 != hipSuccess || e2 != hipSuccess)) e = e1 != hipSuccess ? e1 : e2;
-        }
-        hipGraphExec_t ex = nullptr;
-        if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-        if (g) hipGraphDestroy(g);
-        hipStreamDestroy(cap);
-        if (e != hipSuccess) return hip_fail(e, "graph capture of the persistent filter");
-        it = ctx->graphs.emplace(key, ex).first;
-    }
-    PAF_HIP(hipGraphLaunch(it->second, stream), "hipGraphLaunch");
+    return run_graph(ctx, key, stream, [&](hipStream_t s) -> paf_status {
+        PAF_HIP(launch_fill_u32(ctx->d_queue, 0u, 1, s), "queue reset");
+        PAF_HIP(launch_filter(p, eng, general, emax, sh, s), "filter launch");
+        return PAF_OK;
+    });
+}
+
+paf_status ensure_bucket_ws(paf_ctx* ctx, uint64_t n) {
+    if (ctx->ws_cap >= n && ctx->ws_hist) return PAF_OK;
+    hipFree(ctx->ws_pred);
+    hipFree(ctx->ws_perm);
+    hipFree(ctx->ws_hist);
+    hipFree(ctx->ws_bucket);
+    hipFree(ctx->ws_counts);
+    ctx->ws_pred = nullptr;
+    ctx->ws_perm = ctx->ws_hist = ctx->ws_counts = nullptr;
+    ctx->ws_bucket = nullptr;
+    ctx->ws_cap = 0;
+    // Drop cached graphs: they may point at the old workspace.
+    for (auto& kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+    ctx->graphs.clear();
+    if (hipMalloc(&ctx->ws_perm, n * 4) != hipSuccess || hipMalloc(&ctx->ws_bucket, n) != hipSuccess ||
+        hipMalloc(&ctx->ws_counts, bucket_count_words(n) * 4) != hipSuccess ||
+        hipMalloc(&ctx->ws_hist, 16 * 4) != hipSuccess)
+        return fail(PAF_ERR_NOMEM, "bucketing workspace");
+    ctx->ws_cap = n;
     return PAF_OK;
 }
 
@@ -239,20 +269,12 @@ paf_status paf_destroy(paf_ctx* ctx) {
     hipDeviceSynchronize();
     for (auto& kv : ctx->graphs) hipGraphExecDestroy(kv.second);
     hipFree(ctx->d_err);
-    if (ctx->mlp.master) {
-        hipFree(ctx->mlp.master);
-        hipFree(ctx->mlp.w16);
-        hipFree(ctx->mlp.adam_m);
-        hipFree(ctx->mlp.adam_v);
-        hipFree(ctx->mlp.grad);
-    }
-    if (ctx->mlp.act) hipFree(ctx->mlp.act);
-    hipFree(ctx->ws_feat);
+    mlp_free(ctx->mlp);
     hipFree(ctx->ws_pred);
     hipFree(ctx->ws_perm);
     hipFree(ctx->ws_hist);
     hipFree(ctx->ws_bucket);
-    for (int f = 0; f < 3; ++f) hipFree(ctx->ws_cnt[f]);
+    hipFree(ctx->ws_counts);
     delete ctx;
     return PAF_OK;
 }
@@ -447,6 +469,73 @@ paf_status paf_autotune(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, 
     if (best_ms) *best_ms = best_t;
     if (default_ms) *default_ms = def_t;
     return PAF_OK;
+}
+
+paf_status paf_mlp_predict(paf_ctx* ctx, const paf_batch* batch, float* pred, void* stream) {
+    FilterParams p;
+    paf_status st = check_batch(ctx, batch, PAF_SNEAKYSNAKE, p);
+    if (st != PAF_OK) return st;
+    if (!pred) return fail(PAF_ERR_ARG, "pred is NULL");
+    if (!ctx->mlp_ready) return fail(PAF_ERR_STATE, "no cost model: call paf_mlp_set_params first");
+    PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    PAF_HIP(launch_learned_buckets(ctx->mlp, p, ctx->num_cus, pred, nullptr, (hipStream_t)stream),
+            "cost model launch");
+    return PAF_OK;
+}
+
+paf_status paf_bucket(paf_ctx* ctx, const paf_batch* batch, const float* pred, uint32_t* perm, uint32_t* hist,
+                      void* stream) {
+    FilterParams p;
+    paf_status st = check_batch(ctx, batch, PAF_SNEAKYSNAKE, p);
+    if (st != PAF_OK) return st;
+    if (!pred || !perm || !hist) return fail(PAF_ERR_ARG, "pred/perm/hist is NULL");
+    if ((st = ensure_bucket_ws(ctx, p.n_pairs)) != PAF_OK) return st;
+    PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    PAF_HIP(launch_bucket_from_pred(p, pred, ctx->ws_bucket, s), "bucket keys");
+    PAF_HIP(launch_bucket_sort(ctx->ws_bucket, p.n_pairs, ctx->ws_counts, perm, hist, s), "bucket sort");
+    return PAF_OK;
+}
+
+paf_status paf_filter_bucketed(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, const paf_out* out,
+                               void* stream) {
+    FilterParams p;
+    paf_status st = check_batch(ctx, batch, filters, p);
+    if (st != PAF_OK) return st;
+    if ((st = check_out(out, filters)) != PAF_OK) return st;
+    if (!ctx->mlp_ready) return fail(PAF_ERR_STATE, "no cost model: call paf_mlp_set_params first");
+    const int emax = emax_bucket((int)p.max_E);
+    if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
+    PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    if ((st = ensure_bucket_ws(ctx, p.n_pairs)) != PAF_OK) return st;
+    FilterParams q = p;
+    q.perm = ctx->ws_perm;
+    for (int f = 0; f < 3; ++f) {
+        q.acc[f] = nullptr;
+        q.cnt[f] = ((filters >> f) & 1u) ? out->count[f] : nullptr;
+    }
+    const Engine eng = engine_for(filters);
+    const paf_layout L = layout_for(ctx, p, emax);
+    paf_ctx::GraphKey key{0, 0, 0, 0};
+    const uint64_t* words = reinterpret_cast<const uint64_t*>(&q);
+    for (size_t i = 0; i < sizeof(q) / 8; ++i) key.a = mix(key.a, words[i]);
+    key.b = mix(mix(0xB0C4E7ull, (uint64_t)emax), (uint64_t)L.waves_per_block);
+    key.c = mix(mix(L.blocks_per_cu, L.tiles_per_grab), (uint64_t)(uintptr_t)out->accept_bits[0]);
+    key.d = mix(mix((uint64_t)(uintptr_t)out->accept_bits[1], (uint64_t)(uintptr_t)out->accept_bits[2]),
+                p.n_pairs);
+    return run_graph(ctx, key, (hipStream_t)stream, [&](hipStream_t s) -> paf_status {
+        PAF_HIP(launch_learned_buckets(ctx->mlp, p, ctx->num_cus, nullptr, ctx->ws_bucket, s), "cost model");
+        PAF_HIP(launch_bucket_sort(ctx->ws_bucket, p.n_pairs, ctx->ws_counts, ctx->ws_perm, ctx->ws_hist, s),
+                "bucket sort");
+        paf_status r = run_persistent(ctx, q, eng, emax, L, s, false);
+        if (r != PAF_OK) return r;
+        for (int f = 0; f < 3; ++f)
+            if ((filters >> f) & 1u)
+                PAF_HIP(launch_accept_from_counts(out->count[f], p.len, p.uniform_len, p.E, p.uniform_E, p.max_len,
+                                                  p.max_E, p.n_pairs, out->accept_bits[f], s),
+                        "accept bits");
+        return PAF_OK;
+    });
 }
 
 }  // extern "C"

@@ -49,6 +49,18 @@ struct LaunchShape {
     size_t lds_bytes;
 };
 
+// api.hip: error reporting and batch checks shared by every entry point.
+paf_status fail(paf_status st, const std::string& msg);
+paf_status hip_fail(hipError_t e, const char* what);
+paf_status check_batch(const paf_ctx* ctx, const paf_batch* b, uint32_t filters, FilterParams& p);
+inline uint32_t words_for(uint32_t m) { return (m + 31u) / 32u; }
+
+#define PAF_HIP(call, what)                                        \
+    do {                                                           \
+        hipError_t e_ = (call);                                    \
+        if (e_ != hipSuccess) return ::paf::hip_fail(e_, what);    \
+    } while (0)
+
 // filter.hip
 int emax_bucket(int max_E);  // smallest instantiated EMAX >= max_E, or -1
 hipError_t launch_filter(const FilterParams& p, Engine eng, bool general, int emax,
@@ -64,25 +76,32 @@ const void* filter_kernel_ptr(Engine eng, bool general, int emax);
 size_t filter_lds_bytes(uint32_t waves_per_block, uint32_t wmax);
 
 // mlp.hip
-hipError_t launch_features(const FilterParams& p, float* feat, hipStream_t s);
 struct MlpDev {
-    float* master;      // PAF_MLP_NPARAMS fp32 master weights
-    uint16_t* w16;      // bf16 working copies of W1, W2, W3 (same offsets as master for W's)
-    float* adam_m;
-    float* adam_v;
-    float* grad;        // PAF_MLP_NPARAMS
-    float* act;         // workspace for training activations
-    size_t act_cap;     // rows
-    int step;
+    float* master = nullptr;  // PAF_MLP_NPARAMS fp32 master weights (host layout of paf.h)
+    float* adam_m = nullptr;
+    float* adam_v = nullptr;
+    float* grad = nullptr;    // PAF_MLP_NPARAMS
+    // bf16 working copies (stored as raw 16-bit words)
+    uint16_t* w1b = nullptr;  // [128][64]   W1[h][f]
+    uint16_t* w2b = nullptr;  // [128][128]  W2[o][h]
+    uint16_t* w2tb = nullptr; // [128][128]  W2[o][h] stored as [h][o]
+    float* w3r = nullptr;     // [128] bf16-rounded W3 values held in fp32
+    uint16_t* w1f = nullptr;  // W1 in matrix-core fragment order [8][2][64][8]
+    uint16_t* w2f = nullptr;  // W2 in fragment order, K permuted [8][4][64][8]
+    // training workspace
+    void* ws = nullptr;
+    size_t ws_rows = 0;       // padded batch rows the workspace holds
+    int step = 0;
 };
+size_t bucket_count_words(uint64_t n);
+hipError_t launch_learned_buckets(const MlpDev& m, const FilterParams& p, int num_cus, float* pred,
+                                  uint8_t* bucket, hipStream_t s);
+hipError_t launch_bucket_from_pred(const FilterParams& p, const float* pred, uint8_t* bucket, hipStream_t s);
+hipError_t launch_bucket_sort(const uint8_t* bucket, uint64_t n, uint32_t* counts, uint32_t* perm,
+                              uint32_t* hist, hipStream_t s);
+hipError_t mlp_alloc(MlpDev& m);
+void mlp_free(MlpDev& m);
 hipError_t mlp_round_weights(MlpDev& m, hipStream_t s);
-hipError_t mlp_forward(const MlpDev& m, const float* feat, uint64_t n, float* out, hipStream_t s);
-hipError_t mlp_train_step(MlpDev& m, const float* feat, const float* tgt, uint64_t n, float lr,
-                          float* loss, hipStream_t s);
-hipError_t launch_bucket(const FilterParams& p, const float* pred, uint32_t* perm, uint32_t* hist,
-                         uint32_t* ws, hipStream_t s);
-size_t bucket_ws_words(uint64_t n);
-
 }  // namespace paf
 
 struct paf_ctx {
@@ -102,12 +121,11 @@ struct paf_ctx {
     std::map<GraphKey, hipGraphExec_t> graphs;
     paf::MlpDev mlp{};
     bool mlp_ready = false;
-    // bucketed-pipeline workspace
-    float* ws_feat = nullptr;
+    // bucketed-pipeline workspace (grows to the largest batch seen)
     float* ws_pred = nullptr;
+    uint8_t* ws_bucket = nullptr;
     uint32_t* ws_perm = nullptr;
+    uint32_t* ws_counts = nullptr;
     uint32_t* ws_hist = nullptr;
-    uint32_t* ws_bucket = nullptr;
-    uint16_t* ws_cnt[3] = {nullptr, nullptr, nullptr};
     uint64_t ws_cap = 0;
 };

@@ -1,0 +1,275 @@
+"""The learned cost model: the float64 reference pinned on the CPU, and the
+device kernels (features, matrix-core forward, gradients, Adam, fused
+inference, bucketing, bucketed filter) against it on the GPU.
+
+Tolerances: the device rounds the features and every weight matrix to bf16
+(as the reference does) and also rounds the hidden activations to bf16 before
+the next matrix product, with fp32 accumulation.  One bf16 rounding has
+relative error <= 2^-9; through two layers and the head that is a few parts
+in 10^3 of the output's scale, so outputs and gradients are compared
+normwise at 2e-2 relative (elementwise on predictions at 2e-2 of the output
+scale)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import oracle.mlp as om
+import pairgen
+
+# ------------------------------------------------------------------ CPU pins
+
+
+def _torch_forward(w, X):
+    t = {k: torch.tensor(np.asarray(v), dtype=torch.float64) for k, v in w.items()}
+    x = torch.tensor(X, dtype=torch.float64)
+    h1 = torch.relu(torch.nn.functional.linear(x, t["W1"], t["b1"]))
+    h2 = torch.relu(torch.nn.functional.linear(h1, t["W2"], t["b2"]))
+    return (h2 @ t["W3"] + t["b3"]).numpy()
+
+
+def test_oracle_forward_matches_torch():
+    w = om.working_weights(pairgen.init_mlp_params())
+    X = np.random.default_rng(1).random((50, 64))
+    y, _ = om.forward(w, X)
+    assert np.allclose(y, _torch_forward(w, X), rtol=1e-12, atol=1e-12)
+
+
+def test_oracle_gradients_match_finite_differences():
+    rng = np.random.default_rng(2)
+    w = om.working_weights(pairgen.init_mlp_params())
+    w["b1"] = rng.normal(0, 0.1, 128)   # keep units away from the ReLU kink
+    w["b2"] = rng.normal(0, 0.1, 128)
+    X = rng.random((6, 64))
+    t = rng.random(6) * 10
+    _, g = om.loss_and_grads(w, X, t)
+    eps = 1e-6
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        flat = np.atleast_1d(np.asarray(w[k], np.float64)).reshape(-1)
+        for idx in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+            def loss_at(v):
+                w2 = dict(w)
+                a = flat.copy()
+                a[idx] = v
+                w2[k] = a.reshape(np.shape(w[k])) if np.ndim(w[k]) else a[0]
+                return om.loss_and_grads(w2, X, t)[0]
+            fd = (loss_at(flat[idx] + eps) - loss_at(flat[idx] - eps)) / (2 * eps)
+            an = np.atleast_1d(g[k]).reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (k, idx, fd, an)
+
+
+def test_oracle_adam_matches_torch():
+    rng = np.random.default_rng(3)
+    p0 = rng.normal(size=100)
+    grads = [rng.normal(size=100) for _ in range(3)]
+    tp = torch.tensor(p0.copy(), requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    m = v = np.zeros(100)
+    p = p0.copy()
+    for s, g in enumerate(grads, 1):
+        opt.zero_grad()
+        tp.grad = torch.tensor(g)
+        opt.step()
+        p, m, v = om.adam_step(p, g, m, v, s, 1e-3)
+    assert np.allclose(p, tp.detach().numpy(), rtol=0, atol=1e-12)
+
+
+def test_bf16_rounding_matches_torch():
+    x = np.random.default_rng(4).normal(size=10000).astype(np.float32) * 10
+    x[:4] = [1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -0.0, 3.0]   # ties and specials
+    ref = torch.tensor(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(om.bf16_round(x), ref)
+
+
+def cost_level(y, m, E, max_len, max_E):
+    """The bucketing key as documented in include/paf.h, computed on the host
+    in the same precision (one exact float32 scaling, then integers)."""
+    yc = np.float32(min(max(np.float32(y), np.float32(0)), np.float32(32)))
+    if np.isnan(np.float32(y)):
+        yc = np.float32(0)
+    yq = int(np.floor(yc * np.float32(8)))
+    lim = 8 * (E + 1)
+    steps8 = min(yq, lim) + 8
+    trav = m if yq <= lim else (m * lim) // yq
+    win = (trav + 31) // 32 if trav else 1
+    u = 8 * (win - 1) + (8 * steps8) // (lim + 9)
+    umax = 8 * ((max_len + 31) // 32)
+    return min(15, (16 * u) // umax)
+
+
+def test_cost_key_properties():
+    # More predicted obstacles past E+1 means a shorter run: non-increasing work.
+    prev = None
+    for y in np.linspace(0, 40, 321):
+        c = cost_level(y, 250, 10, 250, 10)
+        if y > 11 and prev is not None:
+            assert c <= prev
+        prev = c
+    # A likely accept rides its pipes through every window: the longest work.
+    assert cost_level(0.0, 250, 10, 250, 10) > cost_level(32.0, 250, 10, 250, 10)
+    assert 0 <= cost_level(1e9, 512, 31, 512, 31) <= 15
+    assert cost_level(0.0, 512, 31, 512, 31) >= 14
+    # Longer pairs (more windows) rank higher at the same prediction.
+    assert cost_level(3.0, 300, 15, 300, 15) > cost_level(3.0, 64, 3, 300, 15)
+
+
+# ------------------------------------------------------------------ GPU
+
+gpu = pytest.mark.gpu
+
+
+def _workload_batch(ctx, w, n, first=0):
+    from paper_1910_03936_amd import costmodel
+    return costmodel.pack_workload(ctx, w, first, n, torch.device("cuda", 0))
+
+
+@gpu
+def test_features_match_oracle(gpu_ctx):
+    for w in (pairgen.UNEVEN_MIX, pairgen.FIXED_250BP.with_E(25), pairgen.FIXED_250BP.with_E(31)):
+        n = 3000
+        b = _workload_batch(gpu_ctx, w, n)
+        f = gpu_ctx.features(b).cpu().numpy()
+        p = pairgen.generate(w, 0, n)
+        want = oracle.features_batch(p.reads, p.refs, p.len, p.E)
+        assert np.allclose(f, want, rtol=0, atol=1e-6), np.abs(f - want).max()
+    gpu_ctx.check()
+
+
+def _set_random_model(ctx, seed=5, bias_scale=0.05):
+    p = pairgen.init_mlp_params(pairgen.SEED_BASE + seed)
+    rng = np.random.default_rng(seed)
+    p[8192:8320] = rng.normal(0, bias_scale, 128)
+    p[24704:24832] = rng.normal(0, bias_scale, 128)
+    p[24960] = 3.0
+    ctx.mlp_set_params(p)
+    return p
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-30))
+
+
+@gpu
+def test_forward_and_fused_predict_match_oracle(gpu_ctx):
+    p = _set_random_model(gpu_ctx)
+    w = om.working_weights(p)
+    n = 5000
+    b = _workload_batch(gpu_ctx, pairgen.UNEVEN_MIX, n)
+    feats = gpu_ctx.features(b)
+    y_gemm = gpu_ctx.mlp_forward(feats).cpu().numpy()
+    y_fused = gpu_ctx.mlp_predict(b).cpu().numpy()
+    X = om.bf16_round(feats.cpu().numpy())
+    y_ref, _ = om.forward(w, X)
+    scale = np.abs(y_ref).max() + 1.0
+    assert np.abs(y_gemm - y_ref).max() <= 2e-2 * scale
+    assert np.abs(y_fused - y_ref).max() <= 2e-2 * scale
+    assert _rel(y_fused, y_ref) <= 2e-2 and _rel(y_gemm, y_ref) <= 2e-2
+
+
+@gpu
+@pytest.mark.parametrize("n", [1, 100, 4096, 5000])
+def test_gradients_match_oracle(gpu_ctx, n):
+    p = _set_random_model(gpu_ctx, seed=6)
+    w = om.working_weights(p)
+    b = _workload_batch(gpu_ctx, pairgen.UNEVEN_MIX, n, first=123)
+    feats = gpu_ctx.features(b)
+    t = torch.linspace(0, 30, n, device="cuda", dtype=torch.float32)
+    loss, grads = gpu_ctx.mlp_train_step(feats, t, lr=0.0, want_grads=True)
+    torch.cuda.synchronize()
+    X = om.bf16_round(feats.cpu().numpy())
+    ref_loss, g = om.loss_and_grads(w, X, t.cpu().numpy())
+    gd = om.unpack(grads.cpu().numpy().astype(np.float64))
+    assert abs(loss.item() - ref_loss) <= 2e-2 * ref_loss
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        assert _rel(gd[k], g[k]) <= 3e-2, (k, _rel(gd[k], g[k]))
+    # lr = 0 leaves the weights alone
+    assert np.array_equal(gpu_ctx.mlp_get_params(), p)
+
+
+@gpu
+def test_adam_step_matches_oracle(gpu_ctx):
+    p = _set_random_model(gpu_ctx, seed=8)
+    b = _workload_batch(gpu_ctx, pairgen.UNEVEN_MIX, 2048)
+    feats = gpu_ctx.features(b)
+    t = torch.full((2048,), 7.0, device="cuda")
+    m = v = np.zeros(om.NPARAMS)
+    master = p.astype(np.float64)
+    for step in (1, 2):
+        _, grads = gpu_ctx.mlp_train_step(feats, t, lr=0.0, want_grads=True)
+        g = grads.cpu().numpy().astype(np.float64)
+        gpu_ctx.mlp_train_step(feats, t, lr=1e-3)
+        master, m, v = om.adam_step(master, g, m, v, step, 1e-3)
+        got = gpu_ctx.mlp_get_params().astype(np.float64)
+        assert np.abs(got - master).max() <= 1e-6 + 1e-5 * np.abs(master).max()
+
+
+@gpu
+def test_training_learns(gpu_ctx):
+    from paper_1910_03936_amd import costmodel
+    losses = costmodel.train(gpu_ctx, pairgen.UNEVEN_MIX, n=200_000, epochs=3, batch=4096, lr=2e-3)
+    assert losses[-1] < losses[0]
+    # Held-out pairs: the model beats predicting the mean label.
+    feats, labels = costmodel.training_set(gpu_ctx, pairgen.UNEVEN_MIX.with_seed(99), 20000)
+    pred = gpu_ctx.mlp_forward(feats).cpu().numpy()
+    lab = (labels.to(torch.int32) & 0xFFFF).cpu().numpy().astype(np.float64)
+    mse = np.mean((pred - lab) ** 2)
+    assert mse < 0.5 * np.var(lab), (mse, np.var(lab))
+
+
+@gpu
+def test_labels_are_the_oracles_counts(gpu_ctx):
+    from paper_1910_03936_amd import costmodel
+    w = pairgen.UNEVEN_MIX.with_seed(77)
+    feats, labels = costmodel.training_set(gpu_ctx, w, 3000)
+    p = pairgen.generate(w, 0, 3000)
+    want = oracle.filter_batch(p.reads, p.refs, p.len, costmodel.LABEL_E)[oracle.SNEAKYSNAKE][1]
+    assert np.array_equal((labels.to(torch.int32) & 0xFFFF).cpu().numpy(), want.astype(np.int64))
+
+
+@gpu
+def test_bucket_permutation(gpu_ctx):
+    _set_random_model(gpu_ctx, seed=9)
+    n = 70_000
+    w = pairgen.UNEVEN_MIX
+    b = _workload_batch(gpu_ctx, w, n)
+    pred = gpu_ctx.mlp_predict(b)
+    perm, hist = gpu_ctx.bucket(b, pred)
+    torch.cuda.synchronize()
+    perm = perm.cpu().numpy().astype(np.int64)
+    hist = hist.cpu().numpy()
+    y = pred.cpu().numpy()
+    p = pairgen.generate(w, 0, n)
+    lev = np.array([cost_level(y[i], int(p.len[i]), int(p.E[i]), int(p.len.max()), int(p.E.max()))
+                    for i in range(n)])
+    bucket = 15 - lev
+    assert np.array_equal(np.sort(perm), np.arange(n))           # a permutation
+    assert np.array_equal(np.bincount(bucket, minlength=16), hist)
+    bp = bucket[perm]
+    assert np.all(np.diff(bp) >= 0)                                # grouped by bucket
+    for k in range(16):                                            # stable inside a bucket
+        ids = perm[bp == k]
+        assert np.all(np.diff(ids) > 0)
+
+
+@gpu
+@pytest.mark.parametrize("filters", [1, 7])
+def test_bucketed_filter_equals_plain(gpu_ctx, filters):
+    _set_random_model(gpu_ctx, seed=10)
+    for w, n in ((pairgen.UNEVEN_MIX, 20_001), (pairgen.FIXED_250BP, 9_000)):
+        b = _workload_batch(gpu_ctx, w, n)
+        plain = gpu_ctx.filter(b, filters)
+        buck = gpu_ctx.filter_bucketed(b, filters)
+        buck2 = gpu_ctx.filter_bucketed(b, filters)   # graph replay
+        torch.cuda.synchronize()
+        for f in plain:
+            for got in (buck, buck2):
+                assert torch.equal(plain[f][0], got[f][0])
+                assert torch.equal(plain[f][1], got[f][1])
+        p = pairgen.generate(w, 0, n)
+        want = oracle.filter_batch(p.reads, p.refs, p.len, p.E, filters)
+        import paper_1910_03936_amd as paf
+        for f in want:
+            acc = paf.accept_bits_to_bool(buck[f][0], n).cpu().numpy().astype(np.uint8)
+            assert np.array_equal(acc, want[f][0])
+            assert np.array_equal(paf.counts_u16(buck[f][1]).cpu().numpy(), want[f][1].astype(np.int64))
+    gpu_ctx.check()
