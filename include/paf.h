@@ -138,7 +138,8 @@ paf_status paf_filter_persistent(paf_ctx* ctx, const paf_batch* batch, uint32_t 
 typedef struct {
     uint32_t lanes_per_pair;   /* 1 (pair per lane) */
     uint32_t waves_per_block;  /* 1, 2, 4 or 8 */
-    uint32_t blocks_per_cu;    /* resident blocks per compute unit in the persistent grid */
+    uint32_t blocks_per_cu;    /* resident blocks per compute unit in the persistent grid;
+                                  0 = no work queue: a full grid, one tile per wave */
     uint32_t tiles_per_grab;   /* 64-pair tiles taken per queue access */
 } paf_layout;
 
@@ -203,6 +204,13 @@ paf_status paf_mlp_train(paf_ctx* ctx, const float* features, const uint16_t* la
  * [16]).  pred [device] fp32 [n]. */
 paf_status paf_bucket(paf_ctx* ctx, const paf_batch* batch, const float* pred, uint32_t* perm,
                       uint32_t* hist, void* stream);
+
+/* The filter of paf_filter_persistent over a caller-given order of the pairs
+ * (order [device] uint32 [n], a permutation of 0..n-1; a repeated or
+ * out-of-range id is undefined behaviour).  Outputs land at each pair's
+ * original index, identical to paf_filter's. */
+paf_status paf_filter_ordered(paf_ctx* ctx, const paf_batch* batch, uint32_t filters,
+                              const uint32_t* order, const paf_out* out, void* stream);
 
 /* The learned pipeline end to end: features -> model -> buckets -> persistent
  * filter over the bucketed order -> decisions written at each pair's original

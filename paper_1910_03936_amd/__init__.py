@@ -29,7 +29,7 @@ STATUS = {0: "PAF_OK", 1: "PAF_ERR_ARG", 2: "PAF_ERR_RANGE", 3: "PAF_ERR_DEVICE"
 EXPORTS = ("paf_create", "paf_destroy", "paf_last_error", "paf_check", "paf_pack", "paf_pack_host",
            "paf_filter", "paf_filter_persistent", "paf_autotune", "paf_set_layout", "paf_features",
            "paf_mlp_set_params", "paf_mlp_get_params", "paf_mlp_forward", "paf_mlp_train_step",
-           "paf_mlp_predict", "paf_mlp_train", "paf_bucket", "paf_filter_bucketed")
+           "paf_mlp_predict", "paf_mlp_train", "paf_bucket", "paf_filter_ordered", "paf_filter_bucketed")
 
 
 class PafError(RuntimeError):
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
         "paf_mlp_predict": ([P, ctypes.POINTER(_Batch), P, P]),
         "paf_mlp_train": ([P, P, P, U64, U32, U32, ctypes.c_float, P, P]),
         "paf_filter_bucketed": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
+        "paf_filter_ordered": ([P, ctypes.POINTER(_Batch), U32, P, ctypes.POINTER(_Out), P]),
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -322,6 +323,14 @@ class Context:
         _check(self.lib.paf_bucket(self.h, ctypes.byref(cb), _ptr(pred), _ptr(perm), _ptr(hist),
                                    _stream(stream)))
         return perm, hist
+
+    def filter_ordered(self, batch: Batch, order: torch.Tensor, filters: int = SNEAKYSNAKE,
+                       out: dict | None = None, stream=None) -> dict:
+        out = out or self.alloc_out(batch.n_pairs, filters, batch.device)
+        cb, co = batch.c(), self._out(out)
+        _check(self.lib.paf_filter_ordered(self.h, ctypes.byref(cb), filters, _ptr(order), ctypes.byref(co),
+                                           _stream(stream)))
+        return out
 
     def filter_bucketed(self, batch: Batch, filters: int = SNEAKYSNAKE, out: dict | None = None,
                         stream=None) -> dict:

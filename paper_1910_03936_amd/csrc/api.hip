@@ -100,7 +100,7 @@ paf_layout default_layout() {
     l.lanes_per_pair = 1;
     l.waves_per_block = 4;
     l.blocks_per_cu = 4;
-    l.tiles_per_grab = 1;
+    l.tiles_per_grab = 2;
     return l;
 }
 
@@ -108,7 +108,7 @@ bool layout_ok(const paf_layout& l) {
     return l.lanes_per_pair == 1 &&
            (l.waves_per_block == 1 || l.waves_per_block == 2 || l.waves_per_block == 4 ||
             l.waves_per_block == 8) &&
-           l.blocks_per_cu >= 1 && l.blocks_per_cu <= 64 && l.tiles_per_grab >= 1 &&
+           l.blocks_per_cu <= 64 && l.tiles_per_grab >= 1 &&
            l.tiles_per_grab <= 64;
 }
 
@@ -169,9 +169,19 @@ paf_status run_persistent(paf_ctx* ctx, FilterParams p, Engine eng, int emax, co
     sh.lds_bytes = filter_lds_bytes(L.waves_per_block, p.wmax);
     if (sh.lds_bytes > 160 * 1024) return fail(PAF_ERR_RANGE, "layout needs more LDS than a CU has");
     PAF_HIP(allow_lds(k, sh.lds_bytes), "hipFuncSetAttribute");
+    const uint64_t need = (p.n_tiles + L.waves_per_block - 1) / L.waves_per_block;
+    if (L.blocks_per_cu == 0) {
+        // Full grid, one tile per wave: the hardware dispatcher is the queue.
+        sh.blocks = (uint32_t)need;
+        p.queue = nullptr;
+        p.grab = 1;
+        return [&]() -> paf_status {
+            PAF_HIP(launch_filter(p, eng, general, emax, sh, stream), "filter launch");
+            return PAF_OK;
+        }();
+    }
     const int nb = std::min<int>((int)L.blocks_per_cu, resident_blocks(k, L.waves_per_block, sh.lds_bytes));
     const uint64_t want = (uint64_t)ctx->num_cus * nb;
-    const uint64_t need = (p.n_tiles + L.waves_per_block - 1) / L.waves_per_block;
     sh.blocks = (uint32_t)std::max<uint64_t>(1, std::min(want, need));
     p.queue = ctx->d_queue;
     p.grab = L.tiles_per_grab;
@@ -215,11 +225,16 @@ paf_status ensure_bucket_ws(paf_ctx* ctx, uint64_t n) {
     return PAF_OK;
 }
 
-paf_layout layout_for(paf_ctx* ctx, const FilterParams& p, int emax) {
+// Launch layout: the forced one, else the autotuned one for this class, else
+// the default (work queue for the persistent entry point; a full grid of
+// one-wave blocks for orders given by a permutation, where measured
+// dispatch by the hardware beat the queue).
+paf_layout layout_for(paf_ctx* ctx, const FilterParams& p, int emax, bool queue_default = true) {
     if (ctx->layout_forced) return ctx->forced;
     auto it = ctx->tuned.find(std::make_tuple((int)p.wmax, emax, p.filters));
     if (it != ctx->tuned.end()) return it->second;
-    return default_layout();
+    if (queue_default) return default_layout();
+    return paf_layout{1u, 1u, 0u, 1u};
 }
 
 void set_outputs(FilterParams& p, const paf_out* out) {
@@ -418,14 +433,17 @@ paf_status paf_autotune(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, 
     hipStream_t s = (hipStream_t)stream;
     const Engine eng = engine_for(filters);
     std::vector<paf_layout> cands;
-    for (uint32_t wpb : {1u, 2u, 4u, 8u})
+    for (uint32_t wpb : {1u, 2u, 4u, 8u}) {
+        if (wpb > max_waves(eng)) continue;
+        cands.push_back(paf_layout{1u, wpb, 0u, 1u});   // full grid, no queue
         for (uint32_t bpc : {1u, 2u, 4u, 8u, 16u})
-            for (uint32_t grab : {1u, 4u}) {
+            for (uint32_t grab : {1u, 2u, 4u, 8u}) {
                 paf_layout l{1u, wpb, bpc, grab};
                 if (filter_lds_bytes(wpb, p.wmax) * bpc > 160 * 1024) continue;
-                if (wpb * bpc > 32 || wpb > max_waves(eng)) continue;
+                if (wpb * bpc > 32) continue;
                 cands.push_back(l);
             }
+    }
     hipEvent_t e0, e1;
     PAF_HIP(hipEventCreate(&e0), "hipEventCreate");
     PAF_HIP(hipEventCreate(&e1), "hipEventCreate");
@@ -497,6 +515,33 @@ paf_status paf_bucket(paf_ctx* ctx, const paf_batch* batch, const float* pred, u
     return PAF_OK;
 }
 
+paf_status paf_filter_ordered(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, const uint32_t* order,
+                              const paf_out* out, void* stream) {
+    FilterParams p;
+    paf_status st = check_batch(ctx, batch, filters, p);
+    if (st != PAF_OK) return st;
+    if ((st = check_out(out, filters)) != PAF_OK) return st;
+    if (!order) return fail(PAF_ERR_ARG, "order is NULL");
+    const int emax = emax_bucket((int)p.max_E);
+    if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
+    PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    FilterParams q = p;
+    q.perm = order;
+    for (int f = 0; f < 3; ++f) {
+        q.acc[f] = nullptr;
+        q.cnt[f] = ((filters >> f) & 1u) ? out->count[f] : nullptr;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const paf_layout L = layout_for(ctx, p, emax, false);
+    if ((st = run_persistent(ctx, q, engine_for(filters), emax, L, s, true)) != PAF_OK) return st;
+    for (int f = 0; f < 3; ++f)
+        if ((filters >> f) & 1u)
+            PAF_HIP(launch_accept_from_counts(out->count[f], p.len, p.uniform_len, p.E, p.uniform_E, p.max_len,
+                                              p.max_E, p.n_pairs, out->accept_bits[f], s),
+                    "accept bits");
+    return PAF_OK;
+}
+
 paf_status paf_filter_bucketed(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, const paf_out* out,
                                void* stream) {
     FilterParams p;
@@ -515,7 +560,7 @@ paf_status paf_filter_bucketed(paf_ctx* ctx, const paf_batch* batch, uint32_t fi
         q.cnt[f] = ((filters >> f) & 1u) ? out->count[f] : nullptr;
     }
     const Engine eng = engine_for(filters);
-    const paf_layout L = layout_for(ctx, p, emax);
+    const paf_layout L = layout_for(ctx, p, emax, false);
     paf_ctx::GraphKey key{0, 0, 0, 0};
     const uint64_t* words = reinterpret_cast<const uint64_t*>(&q);
     for (size_t i = 0; i < sizeof(q) / 8; ++i) key.a = mix(key.a, words[i]);

@@ -104,10 +104,22 @@ __device__ __forceinline__ void stage_tile(const FilterParams& P, uint64_t tile,
         // Words past a pair's length are zero already (the packer zeroes the
         // tail of the last word and the layout has no words beyond W).
     } else {
-        for (uint32_t k = 0; k < WM; ++k) {
-            const bool ok = s.valid && k < s.W;
-            rdL[k * kLdsRow + lane] = ok ? P.reads[off + k] : 0ull;
-            rfL[k * kLdsRow + lane] = ok ? P.refs[off + k] : 0ull;
+        // Pairs sit anywhere (offsets, bucketed order): groups of WM adjacent
+        // lanes read one pair's row of words together, so every load
+        // instruction covers whole rows; the row's offset and length come
+        // from the lane that owns the pair.
+        const uint32_t offlo = (uint32_t)off, offhi = (uint32_t)(off >> 32);
+        const uint32_t wv = s.valid ? s.W : 0u;
+        uint32_t pr = (uint32_t)lane / WM, k = (uint32_t)lane - pr * WM;
+        const uint32_t dp = 64u / WM, dk = 64u - dp * WM;
+        for (uint32_t r = 0; r < WM; ++r) {
+            const uint64_t o = ((uint64_t)__shfl(offhi, (int)pr) << 32) | __shfl(offlo, (int)pr);
+            const bool ok = k < (uint32_t)__shfl(wv, (int)pr);
+            rdL[k * kLdsRow + pr] = ok ? P.reads[o + k] : 0ull;
+            rfL[k * kLdsRow + pr] = ok ? P.refs[o + k] : 0ull;
+            pr += dp;
+            k += dk;
+            if (k >= WM) { k -= WM; pr += 1; }
         }
     }
     wave_lds_sync();
@@ -493,17 +505,21 @@ __global__ void __launch_bounds__(ENG == Engine::Snake ? 512 : 256) filter_kerne
         return;
     }
     // Persistent: each wave takes `grab` tiles at a time from the queue until
-    // it runs dry; every wave leaves after its first empty take.
-    while (true) {
-        uint32_t t0 = 0;
-        if (lane == 0) t0 = atomicAdd(P.queue, P.grab);
-        t0 = __shfl(t0, 0);
-        if (t0 >= P.n_tiles) break;
+    // it runs dry; every wave leaves after its first empty take.  The next
+    // take is issued before the current tiles are processed, so the queue's
+    // round trip overlaps the work.
+    uint32_t t0 = 0;
+    if (lane == 0) t0 = atomicAdd(P.queue, P.grab);
+    t0 = __shfl(t0, 0);
+    while (t0 < P.n_tiles) {
+        uint32_t nx = 0;
+        if (lane == 0) nx = atomicAdd(P.queue, P.grab);
         const uint32_t t1 = min(P.n_tiles, t0 + P.grab);
         for (uint32_t t = t0; t < t1; ++t) {
             run(t);
             wave_lds_sync();
         }
+        t0 = __shfl(nx, 0);
     }
 }
 

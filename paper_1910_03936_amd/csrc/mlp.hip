@@ -183,12 +183,46 @@ struct KeyParams {
     uint8_t* bucket;   // optional
 };
 
+constexpr int kKeyWaves = 8;  // waves per block of the fused kernel (weights shared in LDS)
+
+// The words the features need: read words 0..2 and reference words 0..1.
+struct FeatWords {
+    uint64_t r0, r1, r2, f0, f1;
+    uint32_t m, E;
+    bool valid;
+};
+
+__device__ __forceinline__ FeatWords feat_words(const FilterParams& P, uint64_t p) {
+    FeatWords q{0, 0, 0, 0, 0, 0, 0, false};
+    const PairRef r = pair_ref(P, p);
+    q.valid = r.valid;
+    q.m = r.m;
+    q.E = r.E;
+    if (r.valid) {
+        const uint32_t W = (r.m + 31) >> 5;
+        q.r0 = r.rd[0];
+        q.f0 = r.rf[0];
+        if (W > 1) { q.r1 = r.rd[1]; q.f1 = r.rf[1]; }
+        if (W > 2) q.r2 = r.rd[2];
+    }
+    return q;
+}
+
 template <int EF>
-__global__ void __launch_bounds__(256) key_kernel(KeyParams K) {
+__device__ __forceinline__ void features_from_words(const FeatWords& w, float* f) {
+    uint64_t rd[3] = {w.r0, w.r1, w.r2};
+    uint64_t rf[2] = {w.f0, w.f1};
+    pair_features<EF>(rd, rf, w.m, w.E, f);
+}
+
+template <int EF>
+__global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
     __shared__ __attribute__((aligned(16))) uint16_t sW1[8 * 2 * 64 * 8];
     __shared__ __attribute__((aligned(16))) uint16_t sW2[8 * 4 * 64 * 8];
-    __shared__ float sB1[kHid], sB2[kHid], sW3[kHid];
-    __shared__ __attribute__((aligned(16))) uint16_t sX[4][64][72];
+    __shared__ __attribute__((aligned(16))) float sB1[kHid];
+    __shared__ __attribute__((aligned(16))) float sB2[kHid];
+    __shared__ float sW3[kHid];
+    __shared__ __attribute__((aligned(16))) uint16_t sX[kKeyWaves][64][72];
     const FilterParams& P = K.P;
     for (int i = threadIdx.x; i < 8 * 2 * 64; i += blockDim.x)
         reinterpret_cast<uint4*>(sW1)[i] = reinterpret_cast<const uint4*>(K.w1f)[i];
@@ -203,14 +237,15 @@ __global__ void __launch_bounds__(256) key_kernel(KeyParams K) {
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q16 = lane & 15, grp = lane >> 4;
-    const uint32_t stride = gridDim.x * (blockDim.x >> 6);
-    for (uint32_t tile = blockIdx.x * (blockDim.x >> 6) + wave; tile < P.n_tiles; tile += stride) {
+    const uint32_t stride = gridDim.x * kKeyWaves;
+    uint32_t tile = blockIdx.x * kKeyWaves + wave;
+    FeatWords cur = feat_words(P, (uint64_t)tile * 64 + lane);
+    for (; tile < P.n_tiles; tile += stride) {
         const uint64_t p = (uint64_t)tile * 64 + lane;
-        const PairRef r = pair_ref(P, p);
         {
             float f[64];
-            if (r.valid) {
-                pair_features<EF>(r.rd, r.rf, r.m, r.E, f);
+            if (cur.valid) {
+                features_from_words<EF>(cur, f);
             } else {
 #pragma unroll
                 for (int i = 0; i < 64; ++i) f[i] = 0.0f;
@@ -225,6 +260,10 @@ __global__ void __launch_bounds__(256) key_kernel(KeyParams K) {
                 *reinterpret_cast<uint4*>(&sX[wave][lane][8 * c]) = v;
             }
         }
+        const uint32_t m = cur.m, E = cur.E;
+        const bool valid = cur.valid;
+        // Next tile's words are fetched while this tile goes through the model.
+        if (tile + stride < P.n_tiles) cur = feat_words(P, (uint64_t)(tile + stride) * 64 + lane);
         wave_lds_sync();
         // Layer-1 operand B: X^T, lane (pair 16 nt + q16, group grp) holds
         // features 32 kt + 8 grp .. +7 of its pair.
@@ -234,20 +273,22 @@ __global__ void __launch_bounds__(256) key_kernel(KeyParams K) {
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
                 xf[kt][nt] = *reinterpret_cast<const bf16x8*>(&sX[wave][16 * nt + q16][32 * kt + 8 * grp]);
+        // The accumulators start from the bias (C operand of the first product).
         f32x4 acc2[8][4];
 #pragma unroll
-        for (int a = 0; a < 8; ++a)
+        for (int a = 0; a < 8; ++a) {
+            const f32x4 bias2 = *reinterpret_cast<const f32x4*>(&sB2[16 * a + 4 * grp]);
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc2[a][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc2[a][nt] = bias2;
+        }
+#pragma unroll 1
         for (int kt2 = 0; kt2 < 4; ++kt2) {
             bf16x8 b2[4];
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
                 const int mt1 = 2 * kt2 + half;
-                f32x4 acc1[4];
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt) acc1[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                const f32x4 bias1 = *reinterpret_cast<const f32x4*>(&sB1[16 * mt1 + 4 * grp]);
+                f32x4 acc1[4] = {bias1, bias1, bias1, bias1};
 #pragma unroll
                 for (int kt1 = 0; kt1 < 2; ++kt1) {
                     const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&sW1[((mt1 * 2 + kt1) * 64 + lane) * 8]);
@@ -257,10 +298,7 @@ __global__ void __launch_bounds__(256) key_kernel(KeyParams K) {
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const float h = fmaxf(acc1[nt][i] + sB1[16 * mt1 + 4 * grp + i], 0.0f);
-                        b2[nt][4 * half + i] = (__bf16)h;
-                    }
+                    for (int i = 0; i < 4; ++i) b2[nt][4 * half + i] = (__bf16)fmaxf(acc1[nt][i], 0.0f);
             }
 #pragma unroll
             for (int mt2 = 0; mt2 < 8; ++mt2) {
@@ -269,26 +307,23 @@ __global__ void __launch_bounds__(256) key_kernel(KeyParams K) {
                 for (int nt = 0; nt < 4; ++nt) acc2[mt2][nt] = mfma(a2, b2[nt], acc2[mt2][nt]);
             }
         }
-        // Head: y = w3 . relu(layer 2 + b2) + b3; lane l ends with pair l.
-        float s[4];
+        // Head: y = w3 . relu(layer 2) + b3; lane l ends with pair l.
+        float yv = 0.0f;
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             float t = 0.0f;
 #pragma unroll
             for (int mt2 = 0; mt2 < 8; ++mt2)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int o = 16 * mt2 + 4 * grp + i;
-                    t += sW3[o] * fmaxf(acc2[mt2][nt][i] + sB2[o], 0.0f);
-                }
+                for (int i = 0; i < 4; ++i) t += sW3[16 * mt2 + 4 * grp + i] * fmaxf(acc2[mt2][nt][i], 0.0f);
             t += __shfl_xor(t, 16);
             t += __shfl_xor(t, 32);
-            s[nt] = t;
+            if (grp == nt) yv = t;
         }
-        const float y = (grp == 0 ? s[0] : grp == 1 ? s[1] : grp == 2 ? s[2] : s[3]) + b3;
+        const float y = yv + b3;
         if (p < P.n_pairs) {
-            if (K.pred) K.pred[p] = r.valid ? y : 0.0f;
-            if (K.bucket) K.bucket[p] = (uint8_t)(r.valid ? 15u - cost_bucket(y, r.m, r.E, P.max_len, P.max_E) : 15u);
+            if (K.pred) K.pred[p] = valid ? y : 0.0f;
+            if (K.bucket) K.bucket[p] = (uint8_t)(valid ? 15u - cost_bucket(y, m, E, P.max_len, P.max_E) : 15u);
         }
         wave_lds_sync();
     }
@@ -322,33 +357,51 @@ __global__ void __launch_bounds__(256) bucket_count_kernel(const uint8_t* bucket
     if (threadIdx.x < 16) counts[threadIdx.x * nblk + blockIdx.x] = c[threadIdx.x];
 }
 
-// Exclusive scan of `len` words in place (one block of 1024 threads), and the
-// 16 bucket totals (the array is bucket-major, nblk entries per bucket).
+// Exclusive scan of `len` words in place (one block of 1024 threads, tiles of
+// 4096 words read with coalesced loads), and the 16 bucket totals (the array
+// is bucket-major, nblk entries per bucket).
 __global__ void __launch_bounds__(1024) scan_kernel(uint32_t* a, uint32_t len, uint32_t nblk, uint32_t* hist) {
-    __shared__ uint32_t part[1024];
-    const uint32_t t = threadIdx.x, T = blockDim.x;
-    const uint32_t per = (len + T - 1) / T;
-    const uint32_t lo = min(len, t * per), hi = min(len, lo + per);
-    uint32_t sum = 0;
-    for (uint32_t i = lo; i < hi; ++i) sum += a[i];
-    part[t] = sum;
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t carry_s;
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t == 0) carry_s = 0;
     __syncthreads();
-    for (uint32_t off = 1; off < T; off <<= 1) {
-        const uint32_t v = t >= off ? part[t - off] : 0u;
+    for (uint32_t base = 0; base < len; base += 4096) {
+        uint32_t v[4], s = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t i = base + 4 * t + j;
+            v[j] = i < len ? a[i] : 0u;
+            s += v[j];
+        }
+        // inclusive scan of the thread sums inside the wave
+        uint32_t inc = s;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off);
+            if (lane >= (uint32_t)off) inc += o;
+        }
+        if (lane == 63) wsum[wv] = inc;
         __syncthreads();
-        part[t] += v;
+        uint32_t before = carry_s;
+        for (uint32_t w = 0; w < wv; ++w) before += wsum[w];
+        uint32_t run = before + inc - s;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t i = base + 4 * t + j;
+            if (i < len) a[i] = run;
+            run += v[j];
+        }
+        __syncthreads();
+        if (t == 0) {
+            uint32_t tot = 0;
+            for (int w = 0; w < 16; ++w) tot += wsum[w];
+            carry_s += tot;
+        }
         __syncthreads();
     }
-    uint32_t run = t ? part[t - 1] : 0u;
-    for (uint32_t i = lo; i < hi; ++i) {
-        const uint32_t v = a[i];
-        a[i] = run;
-        run += v;
-    }
-    __syncthreads();
     if (hist && t < 16) {
-        const uint32_t total = part[T - 1];
-        const uint32_t end = t < 15 ? a[(t + 1) * nblk] : total;
+        const uint32_t end = t < 15 ? a[(t + 1) * nblk] : carry_s;
         hist[t] = end - a[t * nblk];
     }
 }
@@ -655,11 +708,11 @@ hipError_t launch_learned_buckets(const MlpDev& m, const FilterParams& p, int nu
     kp.pred = pred;
     kp.bucket = bucket;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) != hipSuccess || nb < 1) nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64 * kKeyWaves, 0) != hipSuccess || nb < 1) nb = 1;
     const uint32_t want = (uint32_t)(num_cus * nb);
-    const uint32_t need = (p.n_tiles + 3) / 4;
+    const uint32_t need = (p.n_tiles + kKeyWaves - 1) / kKeyWaves;
     void* args[] = {&kp};
-    return hipLaunchKernel(k, dim3(std::max(1u, std::min(want, need))), dim3(256), args, 0, s);
+    return hipLaunchKernel(k, dim3(std::max(1u, std::min(want, need))), dim3(64 * kKeyWaves), args, 0, s);
 }
 
 hipError_t launch_bucket_from_pred(const FilterParams& p, const float* pred, uint8_t* bucket, hipStream_t s) {

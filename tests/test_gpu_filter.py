@@ -176,3 +176,16 @@ def test_full_size_fixed_250bp_sampled(gpu_ctx):
     got2 = results(gpu_ctx.filter_persistent(b, SS), n)
     assert np.array_equal(got2[SS][0], acc) and np.array_equal(got2[SS][1], cnt)
     gpu_ctx.check()
+
+
+@pytest.mark.parametrize("filters", [SS, ALL])
+def test_ordered_filter_equals_plain(gpu_ctx, filters):
+    """Any caller-given order gives the plain decisions at the original ids."""
+    p = pairgen.generate(pairgen.UNEVEN_MIX, 9, 5000)
+    b = to_device(p, gpu_ctx, per_pair=True, offsets=True)
+    want = oracle_for(p, filters)
+    g = torch.Generator().manual_seed(3)
+    for order in (torch.randperm(p.n, generator=g), torch.arange(p.n - 1, -1, -1)):
+        o = order.to(torch.int32).cuda()
+        assert_parity(results(gpu_ctx.filter_ordered(b, o, filters), p.n), want, "ordered")
+    gpu_ctx.check()
