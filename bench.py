@@ -143,6 +143,11 @@ def main():
     ap.add_argument("--train-pairs", type=int, default=2_000_000)
     ap.add_argument("--no-learned", action="store_true", help="time the plain filter only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="fixed250", choices=["fixed250", "uneven", "learned-uneven", "stream"],
+                    help="fixed250 (default): 10M x 250 bp at E (plain and learned-bucketed); uneven: 50M "
+                         "pairs of mixed lengths in the persistent launch, default vs autotuned layout; "
+                         "learned-uneven: the same batch, learned-bucketed vs plain; stream: 200M pairs "
+                         "streamed from pinned host memory in 8M-pair chunks")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain copy kernel of known size (counter calibration)")
     args = ap.parse_args()
@@ -163,6 +168,9 @@ def main():
     import paper_1910_03936_amd as paf
     from paper_1910_03936_amd import costmodel
 
+    if args.workload != "fixed250":
+        other_workload(args)
+        return
     dev = torch.device("cuda", 0)
     ctx = paf.Context(0)
     w = pairgen.FIXED_250BP.with_E(args.E)
@@ -267,6 +275,118 @@ def main():
     }
     print(json.dumps(rec), flush=True)
     ctx.close()
+
+
+def emit(args, metric_value, ms, workload_desc, cfg, roofline, cpu, extra):
+    rec = {"metric": "filtered pairs/sec at 250bp E=10, learned-bucketed vs plain; HBM GB/s %peak",
+           "value": metric_value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u64", "data": "synthetic",
+           "config": dict({"workload": workload_desc, "parallelism": "single GPU"}, **cfg),
+           "roofline": roofline, "cpu_baseline": cpu}
+    rec.update(extra)
+    print(json.dumps(rec), flush=True)
+
+
+def other_workload(args):
+    """The uneven-length, learned-uneven and streaming workloads."""
+    import numpy as np
+    import torch
+
+    import pairgen
+    import paper_1910_03936_amd as paf
+    from paper_1910_03936_amd import costmodel
+    from paper_1910_03936_amd.batches import device_batch
+
+    ctx = paf.Context(0)
+    SS = paf.SNEAKYSNAKE
+    if args.workload in ("uneven", "learned-uneven"):
+        w = pairgen.UNEVEN_MIX
+        n = args.pairs or w.n_pairs
+        t = time.perf_counter()
+        b = device_batch(ctx, w, n)
+        total_words = int(b.word_offset[-1].item()) + paf.words_for(int(b.len[-1].item()) & 0xFFFF)
+        log(f"generated and packed {n} uneven pairs ({total_words} words per side) in {time.perf_counter() - t:.1f} s")
+        # algorithmic bytes of the general filter: both sequences, offset, length, E in; count, bit out
+        bytes_total = total_words * 16 + n * (8 + 2 + 1 + 2 + 1 / 8)
+        out = ctx.alloc_out(n, SS, torch.device("cuda", 0))
+
+        def timed(fn):
+            per, tot, _ = time_steps(fn, args.steps, args.warmup)
+            ctx.check()
+            return tot / args.steps, sum(per) / len(per)
+
+        def roof(kern_ms, kernel):
+            a = bytes_total / (kern_ms / 1e3) / 1e9
+            return {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(a / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
+                    "kernel_ms": round(kern_ms, 4), "alg_bytes_per_pair": round(bytes_total / n, 3)}
+
+        ctx.set_layout({"lanes_per_pair": 1, "waves_per_block": 4, "blocks_per_cu": 4, "tiles_per_grab": 2})
+        fixed_ms, fixed_k = timed(lambda: ctx.filter_persistent(b, SS, out=out))
+        ctx.set_layout(None)
+        tuned, best_ms, default_ms = ctx.autotune(b, SS)
+        tuned_ms, tuned_k = timed(lambda: ctx.filter_persistent(b, SS, out=out))
+        log(f"persistent fixed layout {fixed_ms:.3f} ms, autotuned {tuned} {tuned_ms:.3f} ms")
+        cfg = {"pairs": n, "lengths": list(w.lens), "E": "floor(0.05 m)", "filters": "sneakysnake"}
+        if args.workload == "uneven":
+            emit(args, n / (tuned_ms / 1e3), tuned_ms,
+                 f"{n} pairs, lengths {{64,100,150,250,300}}, E=floor(0.05 m), 70% unrelated; one persistent "
+                 f"graph-captured launch, autotuned layout", cfg, roof(tuned_k, "filter_kernel<Snake, E<=15, general>"),
+                 None, {"fixed_layout": {"layout": {"waves_per_block": 4, "blocks_per_cu": 4, "tiles_per_grab": 2},
+                                         "ms_per_step": fixed_ms, "value": n / (fixed_ms / 1e3)},
+                        "autotuned_layout": {"layout": tuned, "ms_per_step": tuned_ms,
+                                             "value": n / (tuned_ms / 1e3)}})
+            return
+        t = time.perf_counter()
+        losses = costmodel.train(ctx, pairgen.TRAIN_MIX, n=args.train_pairs, epochs=4, batch=4096, lr=2e-3)
+        log(f"trained on {args.train_pairs} pairs in {time.perf_counter() - t:.1f} s: {losses}")
+        out_l = ctx.alloc_out(n, SS, torch.device("cuda", 0))
+        learned_ms, _ = timed(lambda: ctx.filter_bucketed(b, SS, out=out_l))
+        same = bool(torch.equal(out[SS][0], out_l[SS][0]) and torch.equal(out[SS][1], out_l[SS][1]))
+        pred = ctx.mlp_predict(b)
+        perm, hist = ctx.bucket(b, pred)
+        ord_ms, ord_k = timed(lambda: ctx.filter_ordered(b, perm, SS, out=out_l))
+        model_ms, _ = timed(lambda: ctx.mlp_predict(b))
+        log(f"learned {learned_ms:.3f} ms vs plain persistent {tuned_ms:.3f} ms, identical: {same}")
+        emit(args, n / (learned_ms / 1e3), learned_ms,
+             f"{n} pairs, lengths {{64,100,150,250,300}}, E=floor(0.05 m), 70% unrelated; learned-bucketed",
+             cfg, roof(ord_k, "filter_kernel<Snake, E<=15, general> in bucketed order"), None,
+             {"plain": {"value": n / (tuned_ms / 1e3), "ms_per_step": tuned_ms, "layout": tuned},
+              "learned": {"value": n / (learned_ms / 1e3), "ms_per_step": learned_ms,
+                          "vs_plain": round(tuned_ms / learned_ms, 3), "identical_decisions": same,
+                          "stages_ms": {"features+model": round(model_ms, 4),
+                                        "filter in bucketed order (+accept bits)": round(ord_ms, 4)},
+                          "bucket_sizes": hist.cpu().tolist(),
+                          "train": {"pairs": args.train_pairs, "epoch_mse": [round(float(x), 3) for x in losses]}}})
+        return
+    # stream
+    from paper_1910_03936_amd.hostbatch import host_batch
+    w = pairgen.STREAM_MIX
+    n = args.pairs or w.n_pairs
+    t = time.perf_counter()
+    hb = host_batch(w, n)
+    log(f"generated and encoded {n} pairs into pinned host memory in {time.perf_counter() - t:.1f} s")
+    costmodel.train(ctx, w, n=args.train_pairs, epochs=4, batch=4096, lr=2e-3)
+    chunk = 8_000_000
+    res = {}
+    for learned in (False, True):
+        paf.stream_filter(ctx, host_batch(w, min(n, 2 * chunk)), chunk, SS, learned)   # warm-up
+        outs, st = paf.stream_filter(ctx, hb, chunk, SS, learned)
+        ctx.check()
+        res[learned] = (outs, st)
+        log(f"stream learned={learned}: {st['seconds']:.3f} s, {n / st['seconds'] / 1e9:.3f} G pairs/s, "
+            f"H2D {st['h2d_bytes'] / st['seconds'] / 1e9:.1f} GB/s")
+    same = all(torch.equal(res[False][0][SS][i], res[True][0][SS][i]) for i in (0, 1))
+    st = res[True][1]
+    emit(args, n / st["seconds"], st["seconds"] * 1e3,
+         f"{n} pairs, lengths {{100,150,250}} 1:1:1, E=m/10, 80% unrelated, streamed from pinned host memory "
+         f"in 8M-pair chunks, learned bucketing on",
+         {"pairs": n, "chunk_pairs": chunk, "filters": "sneakysnake"}, None, None,
+         {"h2d_GBps": st["h2d_bytes"] / st["seconds"] / 1e9, "h2d_bytes": st["h2d_bytes"],
+          "plain": {"value": n / res[False][1]["seconds"], "seconds": res[False][1]["seconds"],
+                    "h2d_GBps": res[False][1]["h2d_bytes"] / res[False][1]["seconds"] / 1e9},
+          "identical_decisions": same})
 
 
 if __name__ == "__main__":

@@ -220,6 +220,38 @@ paf_status paf_filter_ordered(paf_ctx* ctx, const paf_batch* batch, uint32_t fil
 paf_status paf_filter_bucketed(paf_ctx* ctx, const paf_batch* batch, uint32_t filters,
                                const paf_out* out, void* stream);
 
+/* Step a11 -- streaming from host memory (the host-to-accelerator stream of
+ * Ch. 4, Secs. 4.2-4.4).  All pointers [host]; page-locked (pinned) memory
+ * lets the copies overlap the filtering.  Pairs are stored back to back:
+ * pair p's words start at word sum_{q<p} ceil(len[q] / 32) of reads and of
+ * refs (the encoding of paf.h). */
+typedef struct {
+    const uint64_t* reads;
+    const uint64_t* refs;
+    const uint16_t* len;   /* per-pair lengths, 1..max_len */
+    const uint8_t* E;      /* per-pair thresholds, 0..max_E */
+    uint16_t max_len;
+    uint8_t max_E;
+    uint64_t n_pairs;
+} paf_host_batch;
+
+typedef struct {
+    double seconds;    /* wall time of the whole stream */
+    double h2d_bytes;  /* bytes copied host to device */
+    uint64_t chunks;
+} paf_stream_stats;
+
+/* Filters every pair of a host batch, chunk_pairs pairs at a time (a positive
+ * multiple of 64): each chunk is copied on a copy stream into one of two
+ * device buffers while the previous chunk is filtered on a compute stream
+ * (plain batching, or the learned pipeline of paf_filter_bucketed when
+ * `learned` is nonzero), and its decisions are copied back into host_out
+ * (paf_out with [host] pointers: accept bits and counts for all n pairs).
+ * Blocks until every chunk is done.  Decisions equal paf_filter's. */
+paf_status paf_stream_filter(paf_ctx* ctx, const paf_host_batch* batch, uint64_t chunk_pairs,
+                             uint32_t filters, int learned, const paf_out* host_out,
+                             paf_stream_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -126,6 +126,8 @@ def _load():
         lib.pg_generate_ids.argtypes = [ctypes.POINTER(_Cfg), P, ctypes.c_uint64, P, P,
                                         ctypes.c_uint32, P, P, P, P, ctypes.c_int]
         lib.pg_generate_ids.restype = ctypes.c_int
+        lib.pg_lengths.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_uint64, ctypes.c_uint64, P, P, ctypes.c_int]
+        lib.pg_lengths.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -197,6 +199,18 @@ def generate_ids(w: Workload, ids, stride: int | None = None, threads: int | Non
     if rc != 0:
         raise ValueError(f"pairgen rejected workload {w}")
     return Pairs(reads, refs, ln, E, rel, k, ids)
+
+
+def lengths(w: Workload, first: int = 0, n: int | None = None, threads: int | None = None):
+    """(len uint16[n], E uint8[n]) of pairs [first, first + n) without their bases."""
+    lib = _load()
+    n = w.n_pairs - first if n is None else n
+    ln = np.zeros(n, np.uint16)
+    E = np.zeros(n, np.uint8)
+    cfg = w._cfg()
+    if lib.pg_lengths(ctypes.byref(cfg), first, n, _ptr(ln), _ptr(E), threads or default_threads()) != 0:
+        raise ValueError(f"pairgen rejected workload {w}")
+    return ln, E
 
 
 def sample_ids(n_pairs: int, n_sample: int, seed: int = 7) -> np.ndarray:

@@ -180,3 +180,20 @@ int pg_generate_ids(const pg_config* cfg, const uint64_t* ids, uint64_t n,
     }
     return 0;
 }
+
+/* Lengths and thresholds only of pairs [first, first + n): the first draws of
+ * each pair's stream, without its bases. */
+int pg_lengths(const pg_config* cfg, uint64_t first, uint64_t n, uint16_t* len, uint8_t* E, int nthreads) {
+    if (!cfg || cfg->n_len < 1 || cfg->n_len > 8) return -1;
+    if (cfg->fixed_E < 0 && cfg->e_den == 0) return -1;
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(static, 65536)
+    for (int64_t i = 0; i < (int64_t)n; ++i) {
+        pg_rng r;
+        pg_seed(&r, cfg->seed, first + (uint64_t)i);
+        uint32_t m = cfg->lens[cfg->n_len > 1 ? pg_below(&r, cfg->n_len) : 0];
+        len[i] = (uint16_t)m;
+        E[i] = (uint8_t)(cfg->fixed_E >= 0 ? (uint32_t)cfg->fixed_E : (m * cfg->e_num) / cfg->e_den);
+    }
+    return 0;
+}

@@ -29,7 +29,8 @@ STATUS = {0: "PAF_OK", 1: "PAF_ERR_ARG", 2: "PAF_ERR_RANGE", 3: "PAF_ERR_DEVICE"
 EXPORTS = ("paf_create", "paf_destroy", "paf_last_error", "paf_check", "paf_pack", "paf_pack_host",
            "paf_filter", "paf_filter_persistent", "paf_autotune", "paf_set_layout", "paf_features",
            "paf_mlp_set_params", "paf_mlp_get_params", "paf_mlp_forward", "paf_mlp_train_step",
-           "paf_mlp_predict", "paf_mlp_train", "paf_bucket", "paf_filter_ordered", "paf_filter_bucketed")
+           "paf_mlp_predict", "paf_mlp_train", "paf_bucket", "paf_filter_ordered", "paf_filter_bucketed",
+           "paf_stream_filter")
 
 
 class PafError(RuntimeError):
@@ -49,6 +50,16 @@ class _Batch(ctypes.Structure):
 
 class _Out(ctypes.Structure):
     _fields_ = [("accept_bits", ctypes.c_void_p * 3), ("count", ctypes.c_void_p * 3)]
+
+
+class _HostBatch(ctypes.Structure):
+    _fields_ = [("reads", ctypes.c_void_p), ("refs", ctypes.c_void_p), ("len", ctypes.c_void_p),
+                ("E", ctypes.c_void_p), ("max_len", ctypes.c_uint16), ("max_E", ctypes.c_uint8),
+                ("n_pairs", ctypes.c_uint64)]
+
+
+class _StreamStats(ctypes.Structure):
+    _fields_ = [("seconds", ctypes.c_double), ("h2d_bytes", ctypes.c_double), ("chunks", ctypes.c_uint64)]
 
 
 class Layout(ctypes.Structure):
@@ -94,6 +105,8 @@ def load_library(path: str = LIB_PATH):
         "paf_mlp_train": ([P, P, P, U64, U32, U32, ctypes.c_float, P, P]),
         "paf_filter_bucketed": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
         "paf_filter_ordered": ([P, ctypes.POINTER(_Batch), U32, P, ctypes.POINTER(_Out), P]),
+        "paf_stream_filter": ([P, ctypes.POINTER(_HostBatch), U64, U32, I, ctypes.POINTER(_Out),
+                               ctypes.POINTER(_StreamStats)]),
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -339,6 +352,43 @@ class Context:
         _check(self.lib.paf_filter_bucketed(self.h, ctypes.byref(cb), filters, ctypes.byref(co),
                                             _stream(stream)))
         return out
+
+
+@dataclass
+class HostBatch:
+    """Pairs in (pinned) host memory, stored back to back (see paf_host_batch)."""
+    reads: torch.Tensor   # int64 words, CPU
+    refs: torch.Tensor
+    len: torch.Tensor     # int16, CPU
+    E: torch.Tensor       # uint8, CPU
+    max_len: int
+    max_E: int
+
+    @property
+    def n_pairs(self) -> int:
+        return int(self.len.shape[0])
+
+
+def stream_filter(ctx: Context, hb: HostBatch, chunk_pairs: int, filters: int = SNEAKYSNAKE,
+                  learned: bool = False):
+    """paf_stream_filter: returns ({filter: (accept bit words, counts)} in pinned
+    host tensors, stats dict)."""
+    n = hb.n_pairs
+    out = {}
+    o = _Out()
+    for f in range(3):
+        if filters & (1 << f):
+            a = torch.zeros((n + 31) // 32, dtype=torch.int32, pin_memory=True)
+            c = torch.zeros(n, dtype=torch.int16, pin_memory=True)
+            out[1 << f] = (a, c)
+            o.accept_bits[f] = a.data_ptr()
+            o.count[f] = c.data_ptr()
+    b = _HostBatch(hb.reads.data_ptr(), hb.refs.data_ptr(), hb.len.data_ptr(), hb.E.data_ptr(),
+                   hb.max_len, hb.max_E, n)
+    st = _StreamStats()
+    _check(ctx.lib.paf_stream_filter(ctx.h, ctypes.byref(b), chunk_pairs, filters, int(learned),
+                                     ctypes.byref(o), ctypes.byref(st)))
+    return out, {"seconds": st.seconds, "h2d_bytes": st.h2d_bytes, "chunks": int(st.chunks)}
 
 
 def accept_bits_to_bool(bits: torch.Tensor, n: int) -> torch.Tensor:

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpaf.so")
-SOURCES = ["filter.hip", "mlp.hip", "api.hip"]
+SOURCES = ["filter.hip", "mlp.hip", "api.hip", "stream.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -10,7 +10,6 @@ never decides anything; it only orders the work.
 """
 from __future__ import annotations
 
-import numpy as np
 import torch
 
 import pairgen
@@ -20,29 +19,12 @@ from . import SNEAKYSNAKE, Batch, Context
 LABEL_E = 31
 
 
-def pack_workload(ctx: Context, w: pairgen.Workload, first: int, n: int, dev,
+def pack_workload(ctx: Context, w: pairgen.Workload, first: int, n: int, dev=None,
                   chunk: int = 1_000_000) -> Batch:
     """Pairs [first, first + n) of w, packed on the GPU with per-pair lengths,
     thresholds and word offsets."""
-    lens = []
-    Es = []
-    reads = []
-    refs = []
-    for a in range(first, first + n, chunk):
-        q = pairgen.generate(w, a, min(chunk, first + n - a))
-        lens.append(q.len)
-        Es.append(q.E)
-        reads.append(q.reads)
-        refs.append(q.refs)
-    ln = np.concatenate(lens)
-    Ev = np.concatenate(Es)
-    rd = torch.from_numpy(np.concatenate(reads)).to(dev)
-    rf = torch.from_numpy(np.concatenate(refs)).to(dev)
-    b = ctx.pack_pairs(rd, rf, lens=torch.from_numpy(ln.astype(np.int16)).to(dev),
-                       Es=torch.from_numpy(Ev).to(dev), max_len=int(ln.max()), max_E=int(Ev.max()),
-                       offsets=True)
-    del rd, rf
-    return b
+    from .batches import device_batch
+    return device_batch(ctx, w, n, first=first, chunk=chunk, per_pair=True)
 
 
 def labels_for(ctx: Context, b: Batch) -> torch.Tensor:
