@@ -120,7 +120,11 @@ paf_status paf_pack_host(const uint8_t* codes, uint32_t code_stride, const uint1
  * unweighted maze, Eq. 8.2) and run the requested decision stages on them:
  * SneakySnake's greedy traversal (Ch. 8, Sec. 8.4), GateKeeper's Hamming
  * fast path plus amended shifted masks (Ch. 5, Sec. 5.2) and Shouji's
- * sliding-window search (Ch. 6, Sec. 6.2).  filters: mask of PAF_* bits. */
+ * sliding-window search (Ch. 6, Sec. 6.2).  filters: mask of PAF_* bits.
+ * SneakySnake alone runs on the compacting engine (see paf_layout's
+ * chunk_tiles; 8 tiles per chunk, 4 waves per block unless a layout was
+ * forced with paf_set_layout, whose waves_per_block and chunk_tiles then
+ * apply here too; chunk_tiles = 0 selects the per-tile engine). */
 paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, const paf_out* out,
                       void* stream);
 
@@ -141,6 +145,10 @@ typedef struct {
     uint32_t blocks_per_cu;    /* resident blocks per compute unit in the persistent grid;
                                   0 = no work queue: a full grid, one tile per wave */
     uint32_t tiles_per_grab;   /* 64-pair tiles taken per queue access */
+    uint32_t chunk_tiles;      /* SneakySnake alone: 0 = every wave keeps its 64 pairs until
+                                  all are decided; K in 1..16 = a wave owns K tiles and, after
+                                  each 32-column window, regroups the pairs still undecided
+                                  into full waves (the queue then hands out chunks) */
 } paf_layout;
 
 /* Times each candidate layout on `batch` (synchronously, on `stream`),

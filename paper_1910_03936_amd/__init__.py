@@ -64,7 +64,8 @@ class _StreamStats(ctypes.Structure):
 
 class Layout(ctypes.Structure):
     _fields_ = [("lanes_per_pair", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
-                ("blocks_per_cu", ctypes.c_uint32), ("tiles_per_grab", ctypes.c_uint32)]
+                ("blocks_per_cu", ctypes.c_uint32), ("tiles_per_grab", ctypes.c_uint32),
+                ("chunk_tiles", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -66,6 +66,7 @@ paf_status check_batch(const paf_ctx* ctx, const paf_batch* b, uint32_t filters,
     p.filters = filters;
     p.err = ctx->d_err;
     p.grab = 1;
+    p.chunk = 0;
     return PAF_OK;
 }
 
@@ -87,7 +88,7 @@ Engine engine_for(uint32_t filters) {
 }
 
 // Block-size limit of each engine (its launch bound).
-uint32_t max_waves(Engine e) { return e == Engine::Snake ? 8u : 4u; }
+uint32_t max_waves(Engine e) { return e == Engine::Whole ? 4u : 8u; }
 
 hipError_t allow_lds(const void* k, size_t bytes) {
     if (bytes <= 65536) return hipSuccess;
@@ -101,15 +102,19 @@ paf_layout default_layout() {
     l.waves_per_block = 4;
     l.blocks_per_cu = 4;
     l.tiles_per_grab = 2;
+    l.chunk_tiles = 0;
     return l;
 }
+
+// Launch shape of paf_filter's SneakySnake-only launch.
+paf_layout plain_layout() { return paf_layout{1u, 4u, 0u, 1u, 8u}; }
 
 bool layout_ok(const paf_layout& l) {
     return l.lanes_per_pair == 1 &&
            (l.waves_per_block == 1 || l.waves_per_block == 2 || l.waves_per_block == 4 ||
             l.waves_per_block == 8) &&
            l.blocks_per_cu <= 64 && l.tiles_per_grab >= 1 &&
-           l.tiles_per_grab <= 64;
+           l.tiles_per_grab <= 64 && l.chunk_tiles <= 16;
 }
 
 // Largest resident block count per CU for this kernel and LDS size.
@@ -161,15 +166,21 @@ paf_status run_graph(paf_ctx* ctx, const paf_ctx::GraphKey& key, hipStream_t str
 paf_status run_persistent(paf_ctx* ctx, FilterParams p, Engine eng, int emax, const paf_layout& L,
                           hipStream_t stream, bool use_graph) {
     const bool general = true;
+    // SneakySnake alone with a chunk size: the compacting engine; its queue
+    // and grid count chunks instead of tiles.
+    if (eng == Engine::Snake && L.chunk_tiles > 0) eng = Engine::Chunk;
     const void* k = filter_kernel_ptr(eng, general, emax);
     if (!k) return fail(PAF_ERR_RANGE, "no kernel for this threshold");
     if (L.waves_per_block > max_waves(eng)) return fail(PAF_ERR_ARG, "too many waves per block for this engine");
     LaunchShape sh;
     sh.waves_per_block = L.waves_per_block;
-    sh.lds_bytes = filter_lds_bytes(L.waves_per_block, p.wmax);
+    p.chunk = eng == Engine::Chunk ? L.chunk_tiles : 0u;
+    sh.lds_bytes = eng == Engine::Chunk ? chunk_lds_bytes(L.waves_per_block, general, emax, L.chunk_tiles)
+                                        : filter_lds_bytes(L.waves_per_block, p.wmax);
     if (sh.lds_bytes > 160 * 1024) return fail(PAF_ERR_RANGE, "layout needs more LDS than a CU has");
     PAF_HIP(allow_lds(k, sh.lds_bytes), "hipFuncSetAttribute");
-    const uint64_t need = (p.n_tiles + L.waves_per_block - 1) / L.waves_per_block;
+    const uint64_t units = eng == Engine::Chunk ? (p.n_tiles + p.chunk - 1) / p.chunk : p.n_tiles;
+    const uint64_t need = (units + L.waves_per_block - 1) / L.waves_per_block;
     if (L.blocks_per_cu == 0) {
         // Full grid, one tile per wave: the hardware dispatcher is the queue.
         sh.blocks = (uint32_t)need;
@@ -194,7 +205,7 @@ paf_status run_persistent(paf_ctx* ctx, FilterParams p, Engine eng, int emax, co
     const uint64_t* words = reinterpret_cast<const uint64_t*>(&p);
     for (size_t i = 0; i < sizeof(p) / 8; ++i) key.a = mix(key.a, words[i]);
     key.b = mix(mix((uint64_t)eng, (uint64_t)emax), (uint64_t)L.waves_per_block);
-    key.c = mix(mix(sh.blocks, sh.lds_bytes), L.tiles_per_grab);
+    key.c = mix(mix(mix(sh.blocks, sh.lds_bytes), L.tiles_per_grab), L.chunk_tiles);
     key.d = p.n_pairs;
     return run_graph(ctx, key, stream, [&](hipStream_t s) -> paf_status {
         PAF_HIP(launch_fill_u32(ctx->d_queue, 0u, 1, s), "queue reset");
@@ -234,7 +245,7 @@ paf_layout layout_for(paf_ctx* ctx, const FilterParams& p, int emax, bool queue_
     auto it = ctx->tuned.find(std::make_tuple((int)p.wmax, emax, p.filters));
     if (it != ctx->tuned.end()) return it->second;
     if (queue_default) return default_layout();
-    return paf_layout{1u, 1u, 0u, 1u};
+    return paf_layout{1u, 1u, 0u, 1u, 0u};
 }
 
 void set_outputs(FilterParams& p, const paf_out* out) {
@@ -383,11 +394,23 @@ paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, co
     if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
     set_outputs(p, out);
     const bool general = batch->len || batch->E || batch->word_offset;
-    const Engine eng = engine_for(filters);
+    Engine eng = engine_for(filters);
     LaunchShape sh;
     sh.waves_per_block = p.wmax > 8 ? 2 : 4;
     sh.lds_bytes = filter_lds_bytes(sh.waves_per_block, p.wmax);
-    sh.blocks = (uint32_t)((p.n_tiles + sh.waves_per_block - 1) / sh.waves_per_block);
+    uint64_t units = p.n_tiles;
+    // SneakySnake alone: the compacting engine, as a full grid of chunks
+    // (a forced layout may set its chunk size and block shape, or turn it off).
+    const paf_layout PL = ctx->layout_forced ? ctx->forced : plain_layout();
+    if (eng == Engine::Snake && PL.chunk_tiles > 0) {
+        eng = Engine::Chunk;
+        p.chunk = PL.chunk_tiles;
+        sh.waves_per_block = PL.waves_per_block;
+        sh.lds_bytes = chunk_lds_bytes(sh.waves_per_block, general, emax, p.chunk);
+        if (sh.lds_bytes > 160 * 1024) return fail(PAF_ERR_RANGE, "layout needs more LDS than a CU has");
+        units = (p.n_tiles + p.chunk - 1) / p.chunk;
+    }
+    sh.blocks = (uint32_t)((units + sh.waves_per_block - 1) / sh.waves_per_block);
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     PAF_HIP(allow_lds(filter_kernel_ptr(eng, general, emax), sh.lds_bytes), "hipFuncSetAttribute");
     PAF_HIP(launch_filter(p, eng, general, emax, sh, (hipStream_t)stream), "filter launch");
@@ -435,14 +458,24 @@ paf_status paf_autotune(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, 
     std::vector<paf_layout> cands;
     for (uint32_t wpb : {1u, 2u, 4u, 8u}) {
         if (wpb > max_waves(eng)) continue;
-        cands.push_back(paf_layout{1u, wpb, 0u, 1u});   // full grid, no queue
+        cands.push_back(paf_layout{1u, wpb, 0u, 1u, 0u});   // full grid, no queue
         for (uint32_t bpc : {1u, 2u, 4u, 8u, 16u})
             for (uint32_t grab : {1u, 2u, 4u, 8u}) {
-                paf_layout l{1u, wpb, bpc, grab};
+                paf_layout l{1u, wpb, bpc, grab, 0u};
                 if (filter_lds_bytes(wpb, p.wmax) * bpc > 160 * 1024) continue;
                 if (wpb * bpc > 32) continue;
                 cands.push_back(l);
             }
+        if (eng != Engine::Snake) continue;
+        for (uint32_t K : {4u, 8u, 16u}) {
+            const size_t lds = chunk_lds_bytes(wpb, true, emax, K);
+            if (lds > 160 * 1024) continue;
+            cands.push_back(paf_layout{1u, wpb, 0u, 1u, K});
+            for (uint32_t bpc : {1u, 2u, 4u}) {
+                if (lds * bpc > 160 * 1024 || wpb * bpc > 32) continue;
+                cands.push_back(paf_layout{1u, wpb, bpc, 1u, K});
+            }
+        }
     }
     hipEvent_t e0, e1;
     PAF_HIP(hipEventCreate(&e0), "hipEventCreate");
@@ -565,7 +598,8 @@ paf_status paf_filter_bucketed(paf_ctx* ctx, const paf_batch* batch, uint32_t fi
     const uint64_t* words = reinterpret_cast<const uint64_t*>(&q);
     for (size_t i = 0; i < sizeof(q) / 8; ++i) key.a = mix(key.a, words[i]);
     key.b = mix(mix(0xB0C4E7ull, (uint64_t)emax), (uint64_t)L.waves_per_block);
-    key.c = mix(mix(L.blocks_per_cu, L.tiles_per_grab), (uint64_t)(uintptr_t)out->accept_bits[0]);
+    key.c = mix(mix(mix(L.blocks_per_cu, L.tiles_per_grab), L.chunk_tiles),
+                (uint64_t)(uintptr_t)out->accept_bits[0]);
     key.d = mix(mix((uint64_t)(uintptr_t)out->accept_bits[1], (uint64_t)(uintptr_t)out->accept_bits[2]),
                 p.n_pairs);
     return run_graph(ctx, key, (hipStream_t)stream, [&](hipStream_t s) -> paf_status {

@@ -307,6 +307,254 @@ __device__ void snake_tile(const FilterParams& P, uint64_t tile, int lane, uint6
 }
 
 // ---------------------------------------------------------------------------
+// Compacting SneakySnake engine.
+//
+// A wave owns a chunk of K tiles (64 K pairs) and walks it one 32-column
+// window at a time.  The pairs still undecided after window w are packed,
+// with their snake state, into a list in the wave's LDS and the next pass
+// takes them 64 at a time for window w + 1, so every pass runs full waves
+// however early the other pairs of their tiles stopped.  Window words are
+// read straight from memory (a lane holds any pair of the chunk); nothing
+// but the list lives in LDS.
+//
+// List entry (64 bits): pair index in the chunk (10 bits), column c (9),
+// edits e (5), continuation flag (1), m (10), E (5); plus the dead-diagonal
+// mask of a snake that entered the window inside a pipe, and (general
+// layout) the pair's word offset.
+constexpr uint32_t kChunkMaxTiles = 16;
+
+struct ChunkEntry {
+    uint32_t idx, c, e, m, E;
+    bool cont;
+};
+
+__device__ __forceinline__ uint64_t chunk_pack(const ChunkEntry& t) {
+    return (uint64_t)t.idx | ((uint64_t)t.c << 10) | ((uint64_t)t.e << 19) | ((uint64_t)t.cont << 24) |
+           ((uint64_t)t.m << 25) | ((uint64_t)t.E << 35);
+}
+
+__device__ __forceinline__ ChunkEntry chunk_unpack(uint64_t v) {
+    ChunkEntry t;
+    t.idx = (uint32_t)v & 1023u;
+    t.c = (uint32_t)(v >> 10) & 511u;
+    t.e = (uint32_t)(v >> 19) & 31u;
+    t.cont = ((v >> 24) & 1u) != 0;
+    t.m = (uint32_t)(v >> 25) & 1023u;
+    t.E = (uint32_t)(v >> 35) & 31u;
+    return t;
+}
+
+template <int EMAX, bool GENERAL>
+struct ChunkLds {
+    using DT = typename DeadMask<EMAX>::T;
+    uint64_t* ent;
+    DT* dead;
+    uint64_t* off;   // GENERAL only
+    uint32_t* acc;   // 2 K accept words (plain order)
+};
+
+template <int EMAX, bool GENERAL>
+__device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, int lane,
+                            const ChunkLds<EMAX, GENERAL>& L) {
+    constexpr int D = 2 * EMAX + 1;
+    using DT = typename DeadMask<EMAX>::T;
+    const uint64_t slot0 = (uint64_t)chunk * K * 64u;
+    const uint32_t n_here = (uint32_t)min<uint64_t>((uint64_t)K * 64u, P.n_pairs - slot0);
+    const bool plain_out = !(GENERAL && P.perm);
+    if (plain_out)
+        for (uint32_t j = (uint32_t)lane; j < 2 * K; j += 64) L.acc[j] = 0u;
+    const bool mask_E = GENERAL ? (P.E != nullptr || P.uniform_E < (uint32_t)EMAX)
+                                : (P.uniform_E < (uint32_t)EMAX);
+    uint32_t n_ent = n_here;
+    for (uint32_t w = 0; n_ent > 0; ++w) {
+        wave_lds_sync();
+        uint32_t n_out = 0;
+        for (uint32_t g = 0; g < n_ent; g += 64) {
+            const uint32_t i = g + (uint32_t)lane;
+            bool act = i < n_ent;
+            ChunkEntry t = {};
+            DT dead = 0;
+            uint64_t off = 0;
+            if (w == 0) {
+                t.idx = i;
+                t.c = 0;
+                t.e = 0;
+                t.cont = false;
+                t.m = P.uniform_len;
+                t.E = P.uniform_E;
+                if (act) {
+                    const uint64_t slot = slot0 + i;
+                    if (GENERAL) {
+                        const uint64_t id = P.perm ? P.perm[slot] : slot;
+                        if (P.len) t.m = P.len[id];
+                        if (P.E) t.E = P.E[id];
+                        off = P.word_offset ? P.word_offset[id] : id * (uint64_t)P.stride_words;
+                        L.off[i] = off;
+                        if (t.m < 1 || t.m > P.max_len || t.E > P.max_E) {
+                            atomicOr(P.err, 1u);
+                            P.cnt[0][id] = 0;
+                            act = false;
+                        }
+                    } else {
+                        off = slot * (uint64_t)P.stride_words;
+                    }
+                }
+            } else if (act) {
+                t = chunk_unpack(L.ent[i]);
+                dead = L.dead[i];
+                off = GENERAL ? L.off[t.idx] : (slot0 + t.idx) * (uint64_t)P.stride_words;
+            }
+            const uint32_t m = act ? t.m : 0u;
+            const uint32_t E = t.E;
+            uint32_t c = t.c, e = t.e;
+            const WindowWords q = window_words_direct(P.reads + off, P.refs + off, (int)w,
+                                                      (int)((m + 31) >> 5), (int)m);
+            const bool boundary = wave_any(act && (w == 0 || 32u * (w + 2) > m));
+            uint32_t M[D];
+            build_snake_map<EMAX>(q, boundary, M);
+            if (wave_any(act && t.cont)) {
+                // A snake that entered inside a pipe: diagonals whose pipes
+                // ended before this window hit an obstacle in its first column.
+#pragma unroll
+                for (int d = 0; d < D; ++d) M[d] |= t.cont ? (uint32_t)((dead >> d) & 1u) : 0u;
+            }
+            if (mask_E) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const int dd = d - EMAX;
+                    if ((uint32_t)(dd < 0 ? -dd : dd) > E) M[d] = ~0u;
+                }
+            }
+            const uint32_t w0 = 32u * w, wend = w0 + 32u;
+            bool acc = false, ncont = false;
+            uint32_t s_prev = 0;
+            bool inw = act && c < wend;
+            while (inw) {
+                const uint32_t s = c - w0;
+                uint32_t best = 0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) best = max(best, ffbl(M[d] >> s));
+                const bool clear = best == 0xFFFFFFFFu;
+                const uint32_t R = clear ? wend : c + best;
+                const bool reach = R >= m;
+                const bool obst = !reach && !clear;
+                e += obst ? 1u : 0u;
+                c = reach ? c : (clear ? wend : R + 1u);
+                const bool rej = e > E;
+                const bool fin_acc = reach || (obst && !rej && c >= m);
+                acc = fin_acc;
+                if (clear && !reach) {
+                    ncont = true;
+                    s_prev = s;
+                }
+                act = !(fin_acc || rej);
+                inw = act && c < wend;
+            }
+            const bool fin = (i < n_ent) && !act && m != 0u;
+            if (fin) {
+                const uint64_t slot = slot0 + t.idx;
+                if (plain_out) {
+                    P.cnt[0][slot] = (uint16_t)e;
+                    if (acc) atomicOr(&L.acc[t.idx >> 5], 1u << (t.idx & 31u));
+                } else {
+                    P.cnt[0][P.perm[slot]] = (uint16_t)e;
+                }
+            }
+            // Survivors go on to the next window.
+            DT dm = 0;
+            if (wave_any(act && ncont)) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) dm |= (DT)min(M[d] >> s_prev, 1u) << d;
+            }
+            const uint64_t bal = __ballot(act);
+            const uint32_t pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            if (act) {
+                ChunkEntry u = t;
+                u.c = c;
+                u.e = e;
+                u.cont = ncont;
+                L.ent[n_out + pre] = chunk_pack(u);
+                L.dead[n_out + pre] = ncont ? dm : (DT)0;
+            }
+            n_out += (uint32_t)__builtin_popcountll(bal);
+        }
+        n_ent = n_out;
+    }
+    if (plain_out) {
+        wave_lds_sync();
+        for (uint32_t j = (uint32_t)lane; j < 2 * K; j += 64) {
+            const uint64_t s0 = slot0 + 32u * j;
+            if (s0 < P.n_pairs) P.acc[0][s0 / 32] = L.acc[j];
+        }
+    }
+}
+
+// Bytes of one wave's list in LDS.
+template <int EMAX, bool GENERAL>
+__host__ __device__ constexpr size_t chunk_wave_bytes_t(uint32_t K) {
+    using DT = typename DeadMask<EMAX>::T;
+    return (size_t)K * 64 * (8 + sizeof(DT) + (GENERAL ? 8 : 0)) + (size_t)K * 8;
+}
+
+template <int EMAX, bool GENERAL>
+__global__ void __launch_bounds__(512) chunk_kernel(FilterParams P) {
+    extern __shared__ uint64_t lds[];
+    using DT = typename DeadMask<EMAX>::T;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const uint32_t K = P.chunk;
+    const uint32_t NE = K * 64u;
+    char* b = reinterpret_cast<char*>(lds) + (size_t)wave * chunk_wave_bytes_t<EMAX, GENERAL>(K);
+    ChunkLds<EMAX, GENERAL> L;
+    L.ent = reinterpret_cast<uint64_t*>(b);
+    b += (size_t)NE * 8;
+    if (GENERAL) {
+        L.off = reinterpret_cast<uint64_t*>(b);
+        b += (size_t)NE * 8;
+    } else {
+        L.off = nullptr;
+    }
+    L.dead = reinterpret_cast<DT*>(b);
+    b += (size_t)NE * sizeof(DT);
+    L.acc = reinterpret_cast<uint32_t*>(b);
+    const uint32_t n_chunks = (P.n_tiles + K - 1) / K;
+    if (P.queue == nullptr) {
+        const uint32_t ch = blockIdx.x * (blockDim.x >> 6) + wave;
+        if (ch < n_chunks) chunk_snake<EMAX, GENERAL>(P, ch, K, lane, L);
+        return;
+    }
+    uint32_t c0 = 0;
+    if (lane == 0) c0 = atomicAdd(P.queue, 1u);
+    c0 = __shfl(c0, 0);
+    while (c0 < n_chunks) {
+        uint32_t nx = 0;
+        if (lane == 0) nx = atomicAdd(P.queue, 1u);
+        chunk_snake<EMAX, GENERAL>(P, c0, K, lane, L);
+        wave_lds_sync();
+        c0 = __shfl(nx, 0);
+    }
+}
+
+template <bool GENERAL>
+const void* chunk_kernel_for(int emax) {
+    switch (emax) {
+#define PAF_CASE(X) \
+    case X: return reinterpret_cast<const void*>(&chunk_kernel<X, GENERAL>);
+        PAF_CASE(0) PAF_CASE(1) PAF_CASE(2) PAF_CASE(3) PAF_CASE(4) PAF_CASE(5) PAF_CASE(6)
+        PAF_CASE(7) PAF_CASE(8) PAF_CASE(10) PAF_CASE(12) PAF_CASE(15) PAF_CASE(20) PAF_CASE(25)
+        PAF_CASE(31)
+#undef PAF_CASE
+        default: return nullptr;
+    }
+}
+
+template <bool GENERAL>
+size_t chunk_bytes_for(int emax, uint32_t K) {
+    return emax <= 15 ? chunk_wave_bytes_t<15, GENERAL>(K) : chunk_wave_bytes_t<31, GENERAL>(K);
+}
+
+// ---------------------------------------------------------------------------
 // Whole-map engine.
 
 // GateKeeper's amendment of one window word (Ch. 5, Sec. 5.2.2; SRS of
@@ -601,6 +849,7 @@ int emax_bucket(int max_E) {
 }
 
 const void* filter_kernel_ptr(Engine eng, bool general, int emax) {
+    if (eng == Engine::Chunk) return general ? chunk_kernel_for<true>(emax) : chunk_kernel_for<false>(emax);
     if (eng == Engine::Snake)
         return general ? kernel_for<Engine::Snake, true>(emax) : kernel_for<Engine::Snake, false>(emax);
     return general ? kernel_for<Engine::Whole, true>(emax) : kernel_for<Engine::Whole, false>(emax);
@@ -608,6 +857,11 @@ const void* filter_kernel_ptr(Engine eng, bool general, int emax) {
 
 size_t filter_lds_bytes(uint32_t waves_per_block, uint32_t wmax) {
     return (size_t)waves_per_block * 2 * wmax * kLdsRow * sizeof(uint64_t);
+}
+
+size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_t chunk_tiles) {
+    return (size_t)waves_per_block *
+           (general ? chunk_bytes_for<true>(emax, chunk_tiles) : chunk_bytes_for<false>(emax, chunk_tiles));
 }
 
 hipError_t launch_filter(const FilterParams& p, Engine eng, bool general, int emax,

@@ -30,8 +30,24 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) {
 }
 __device__ __forceinline__ float bf16_round(float x) { return (float)(__bf16)x; }
 
+typedef __attribute__((ext_vector_type(2))) float f32x2;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(2))) short s16x2;
+
+// relu of two fp32 values rounded to bf16, as the packed bf16 bit patterns.
+__device__ __forceinline__ s16x2 relu_pk(float a, float b) {
+    const bf16x2 h = __builtin_convertvector(f32x2{a, b}, bf16x2);
+    const s16x2 v = __builtin_bit_cast(s16x2, h);
+    return __builtin_elementwise_max(v, s16x2{0, 0});
+}
+
 __device__ __forceinline__ f32x4 mfma(const bf16x8& a, const bf16x8& b, const f32x4& c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Layer-1 weight fragment (m-tile mt, k-tile kt) of one lane from LDS.
+__device__ __forceinline__ bf16x8 a1_at(const uint16_t* sW1, int mt, int kt, int lane) {
+    return *reinterpret_cast<const bf16x8*>(&sW1[((mt * 2 + kt) * 64 + lane) * 8]);
 }
 
 // Hidden index carried by element j of lane group g in layer-2 k-tile kt.
@@ -70,22 +86,48 @@ __global__ void round_kernel(const float* master, uint16_t* w1b, uint16_t* w2b, 
 // Features of one pair: [0] = m / 512, [1] = E / 32, slot 32 + d = fraction of
 // matching map cells (vacant cells blocked) over the first min(m, 64)
 // columns of diagonal d, |d| <= min(E, 30).
+// Left-edge vacancy of window 0 for diagonal d < 0: read positions below 0.
+template <int d>
+__device__ __forceinline__ constexpr uint32_t left_vacant() {
+    if constexpr (d >= 0) return 0u;
+    else return (1u << (-d)) - 1u;
+}
+
+template <int EF, int K, int I = 0>
+__device__ __forceinline__ void count_long(const WindowWords& q, uint32_t* z) {
+    if constexpr (I < 2 * EF + 1) {
+        constexpr int d = I - EF;
+        // m >= 64 + EF: no read position of the first two windows lies past the
+        // read, so the only vacant cells are the constant left edge of window 0.
+        const uint32_t mw = diag_raw<d>(q) | (K == 0 ? left_vacant<d>() : 0u);
+        z[I] += __builtin_popcount(~mw);
+        count_long<EF, K, I + 1>(q, z);
+    }
+}
+
 template <int EF>
 __device__ __forceinline__ void pair_features(const uint64_t* rd, const uint64_t* rf, uint32_t m,
-                                              uint32_t E, float* f) {
+                                              uint32_t E, float* f, bool all_long) {
     constexpr int D = 2 * EF + 1;
     uint32_t z[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) z[i] = 0;
     const int W = (int)((m + 31) >> 5);
+    // The fast path doubles the feature code; above 15 diagonals per side it
+    // would push the fused model kernel past its register budget.
+    if (EF <= 15 && all_long) {
+        count_long<EF, 0>(window_words_direct(rd, rf, 0, W, (int)m), z);
+        count_long<EF, 1>(window_words_direct(rd, rf, 1, W, (int)m), z);
+    } else {
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const WindowWords q = window_words_direct(rd, rf, k, W, (int)m);
-        const uint32_t colvalid = ~q.vc;
-        uint32_t M[D];
-        build_diag_blocked<EF>(q, M);
+        for (int k = 0; k < 2; ++k) {
+            const WindowWords q = window_words_direct(rd, rf, k, W, (int)m);
+            const uint32_t colvalid = ~q.vc;
+            uint32_t M[D];
+            build_diag_blocked<EF>(q, M);
 #pragma unroll
-        for (int i = 0; i < D; ++i) z[i] += __builtin_popcount(~M[i] & colvalid);
+            for (int i = 0; i < D; ++i) z[i] += __builtin_popcount(~M[i] & colvalid);
+        }
     }
     const uint32_t cols = m < 64 ? m : 64;
     const float rcp = 1.0f / (float)cols;
@@ -134,7 +176,7 @@ __global__ void __launch_bounds__(256) features_kernel(FilterParams P, float* ou
     const PairRef r = pair_ref(P, p);
     float f[64];
     if (r.valid) {
-        pair_features<EF>(r.rd, r.rf, r.m, r.E, f);
+        pair_features<EF>(r.rd, r.rf, r.m, r.E, f, false);
     } else {
 #pragma unroll
         for (int i = 0; i < 64; ++i) f[i] = 0.0f;
@@ -209,10 +251,10 @@ __device__ __forceinline__ FeatWords feat_words(const FilterParams& P, uint64_t 
 }
 
 template <int EF>
-__device__ __forceinline__ void features_from_words(const FeatWords& w, float* f) {
+__device__ __forceinline__ void features_from_words(const FeatWords& w, float* f, bool all_long) {
     uint64_t rd[3] = {w.r0, w.r1, w.r2};
     uint64_t rf[2] = {w.f0, w.f1};
-    pair_features<EF>(rd, rf, w.m, w.E, f);
+    pair_features<EF>(rd, rf, w.m, w.E, f, all_long);
 }
 
 template <int EF>
@@ -244,8 +286,9 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
         const uint64_t p = (uint64_t)tile * 64 + lane;
         {
             float f[64];
+            const bool all_long = !wave_any(cur.valid && cur.m < 64u + EF);
             if (cur.valid) {
-                features_from_words<EF>(cur, f);
+                features_from_words<EF>(cur, f, all_long);
             } else {
 #pragma unroll
                 for (int i = 0; i < 64; ++i) f[i] = 0.0f;
@@ -273,33 +316,47 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
                 xf[kt][nt] = *reinterpret_cast<const bf16x8*>(&sX[wave][16 * nt + q16][32 * kt + 8 * grp]);
-        // The accumulators start from the bias (C operand of the first product).
         f32x4 acc2[8][4];
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-            const f32x4 bias2 = *reinterpret_cast<const f32x4*>(&sB2[16 * a + 4 * grp]);
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc2[a][nt] = bias2;
-        }
-#pragma unroll 1
-        for (int kt2 = 0; kt2 < 4; ++kt2) {
-            bf16x8 b2[4];
+        // Layer 1 for the two m-tiles 2 kt2, 2 kt2 + 1 gives layer 2's operand
+        // B for k-tile kt2: relu(W1 x + b1) rounded to bf16 (ReLU applied to
+        // the packed bf16 pair as a 16-bit integer max: rounding keeps signs).
+        auto layer1 = [&](int kt2, bf16x8* b2) {
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
                 const int mt1 = 2 * kt2 + half;
                 const f32x4 bias1 = *reinterpret_cast<const f32x4*>(&sB1[16 * mt1 + 4 * grp]);
-                f32x4 acc1[4] = {bias1, bias1, bias1, bias1};
+                f32x4 acc1[4];
 #pragma unroll
-                for (int kt1 = 0; kt1 < 2; ++kt1) {
-                    const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&sW1[((mt1 * 2 + kt1) * 64 + lane) * 8]);
+                for (int nt = 0; nt < 4; ++nt) acc1[nt] = mfma(a1_at(sW1, mt1, 0, lane), xf[0][nt], bias1);
+                const bf16x8 a1b = a1_at(sW1, mt1, 1, lane);
 #pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) acc1[nt] = mfma(a1, xf[kt1][nt], acc1[nt]);
-                }
+                for (int nt = 0; nt < 4; ++nt) acc1[nt] = mfma(a1b, xf[1][nt], acc1[nt]);
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) b2[nt][4 * half + i] = (__bf16)fmaxf(acc1[nt][i], 0.0f);
+                    for (int i = 0; i < 4; i += 2) {
+                        const s16x2 v = relu_pk(acc1[nt][i], acc1[nt][i + 1]);
+                        b2[nt][4 * half + i] = __builtin_bit_cast(__bf16, (short)v[0]);
+                        b2[nt][4 * half + i + 1] = __builtin_bit_cast(__bf16, (short)v[1]);
+                    }
             }
+        };
+        {
+            // k-tile 0: the accumulators start from the bias (C operand).
+            bf16x8 b2[4];
+            layer1(0, b2);
+#pragma unroll
+            for (int mt2 = 0; mt2 < 8; ++mt2) {
+                const f32x4 bias2 = *reinterpret_cast<const f32x4*>(&sB2[16 * mt2 + 4 * grp]);
+                const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(&sW2[((mt2 * 4 + 0) * 64 + lane) * 8]);
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) acc2[mt2][nt] = mfma(a2, b2[nt], bias2);
+            }
+        }
+#pragma unroll 1
+        for (int kt2 = 1; kt2 < 4; ++kt2) {
+            bf16x8 b2[4];
+            layer1(kt2, b2);
 #pragma unroll
             for (int mt2 = 0; mt2 < 8; ++mt2) {
                 const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(&sW2[((mt2 * 4 + kt2) * 64 + lane) * 8]);

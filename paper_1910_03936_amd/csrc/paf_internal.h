@@ -38,10 +38,11 @@ struct FilterParams {
     uint32_t* err;          // sticky range flag
     uint32_t* queue;        // tile counter of the persistent launch, or NULL
     uint32_t grab;          // tiles per queue access
+    uint32_t chunk;         // tiles per wave-owned chunk (compacting engine)
 };
 
 // Kernel selection.
-enum class Engine { Snake, Whole };
+enum class Engine { Snake, Whole, Chunk };
 
 struct LaunchShape {
     uint32_t waves_per_block;
@@ -74,6 +75,7 @@ hipError_t launch_accept_from_counts(const uint16_t* cnt, const uint16_t* len, u
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 const void* filter_kernel_ptr(Engine eng, bool general, int emax);
 size_t filter_lds_bytes(uint32_t waves_per_block, uint32_t wmax);
+size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_t chunk_tiles);
 
 // mlp.hip
 struct MlpDev {

@@ -1,0 +1,120 @@
+"""Compacting SneakySnake engine (pairs regrouped between 32-column windows)
+against the oracle: uniform and per-pair layouts, caller-given orders, both
+dead-mask widths, chunk sizes that leave ragged last chunks, and the launch
+shapes the autotuner may pick."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import pairgen
+import paper_1910_03936_amd as paf
+from gpu_util import assert_parity, oracle_for, results, to_device
+
+pytestmark = pytest.mark.gpu
+SS = paf.SNEAKYSNAKE
+
+
+def _layout(wpb, bpc, K):
+    return {"lanes_per_pair": 1, "waves_per_block": wpb, "blocks_per_cu": bpc, "tiles_per_grab": 1,
+            "chunk_tiles": K}
+
+
+@pytest.fixture
+def ctx(gpu_ctx):
+    yield gpu_ctx
+    gpu_ctx.set_layout(None)
+
+
+@pytest.mark.parametrize("E", [0, 5, 10, 25])
+def test_chunk_fixed_250bp(ctx, E):
+    w = pairgen.FIXED_250BP.with_E(E)
+    p = pairgen.generate(w, 17, 64 * 37 + 5)
+    want = oracle_for(p, SS)
+    b = to_device(p, ctx, per_pair=False, offsets=False)
+    for wpb, K in ((4, 8), (1, 1), (8, 3), (2, 16)):
+        ctx.set_layout(_layout(wpb, 0, K))
+        assert_parity(results(ctx.filter(b, SS), p.n), want, f"plain E={E} wpb={wpb} K={K}")
+        assert_parity(results(ctx.filter_persistent(b, SS), p.n), want, f"full grid E={E} wpb={wpb} K={K}")
+        ctx.set_layout(_layout(wpb, 2, K))
+        assert_parity(results(ctx.filter_persistent(b, SS), p.n), want, f"queue E={E} wpb={wpb} K={K}")
+    ctx.check()
+
+
+def test_chunk_uneven_offsets_and_orders(ctx):
+    p = pairgen.generate(pairgen.UNEVEN_MIX, 23, 6000)
+    want = oracle_for(p, SS)
+    g = torch.Generator().manual_seed(5)
+    for offsets in (True, False):
+        b = to_device(p, ctx, per_pair=True, offsets=offsets)
+        for lay in (_layout(4, 0, 8), _layout(8, 1, 4), _layout(1, 4, 16)):
+            ctx.set_layout(lay)
+            assert_parity(results(ctx.filter(b, SS), p.n), want, f"plain {lay}")
+            assert_parity(results(ctx.filter_persistent(b, SS), p.n), want, f"persistent {lay}")
+            o = torch.randperm(p.n, generator=g).to(torch.int32).cuda()
+            assert_parity(results(ctx.filter_ordered(b, o, SS), p.n), want, f"ordered {lay}")
+    ctx.check()
+
+
+def test_chunk_edge_lengths_and_thresholds(ctx):
+    """Lengths 1..512 around word edges, E from 0 to 31 (and E >= m), pairs
+    that match exactly (pipes that run across every window) and pairs that
+    differ everywhere."""
+    rng = np.random.default_rng(29)
+    rows = []
+    for m in (1, 2, 31, 32, 33, 63, 64, 65, 95, 96, 97, 255, 256, 257, 480, 511, 512):
+        a = rng.integers(0, 4, m).astype(np.uint8)
+        b = a.copy()
+        b[rng.integers(0, m, max(1, m // 40))] ^= 2
+        for ref in (a, b, np.roll(a, 2), np.roll(a, -3), (a + 1) % 4, rng.integers(0, 4, m).astype(np.uint8)):
+            for E in sorted({0, 1, 2, 7, 15, 16, min(31, m - 1), min(31, m), 31}):
+                rows.append((a, ref, m, E))
+    n = len(rows)
+    R = np.zeros((n, 512), np.uint8)
+    F = np.zeros((n, 512), np.uint8)
+    L = np.zeros(n, np.uint16)
+    Ev = np.zeros(n, np.uint8)
+    for i, (a, r, m, E) in enumerate(rows):
+        R[i, :m], F[i, :m], L[i], Ev[i] = a, r, m, E
+    p = pairgen.Pairs(R, F, L, Ev, np.zeros(n, np.uint8), np.zeros(n, np.uint16))
+    want = oracle_for(p, SS)
+    for me in (15, 31):   # 32-bit and 64-bit dead masks
+        sel = np.nonzero(Ev <= me)[0]
+        q = pairgen.Pairs(R[sel], F[sel], L[sel], Ev[sel], np.zeros(sel.size, np.uint8),
+                          np.zeros(sel.size, np.uint16))
+        wq = {SS: (want[SS][0][sel], want[SS][1][sel])}
+        b = to_device(q, ctx, per_pair=True, offsets=True, max_len=512, max_E=me)
+        for lay in (_layout(4, 0, 8), _layout(2, 2, 5)):
+            ctx.set_layout(lay)
+            assert_parity(results(ctx.filter(b, SS), q.n), wq, f"edges max_E={me} {lay}")
+            assert_parity(results(ctx.filter_persistent(b, SS), q.n), wq, f"edges persistent max_E={me} {lay}")
+    ctx.check()
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 511, 512, 513])
+def test_chunk_tiny_batches(ctx, n):
+    p = pairgen.generate(pairgen.FIXED_250BP, 300, n)
+    b = to_device(p, ctx, per_pair=False, offsets=False)
+    want = oracle_for(p, SS)
+    assert_parity(results(ctx.filter(b, SS), n), want, f"n={n}")
+    ctx.set_layout(_layout(8, 0, 16))
+    assert_parity(results(ctx.filter(b, SS), n), want, f"n={n} K=16")
+
+
+def test_chunk_range_violation(ctx):
+    """A pair outside the batch's bounds: count 0, reject, sticky flag; the
+    other pairs are unaffected."""
+    p = pairgen.generate(pairgen.UNEVEN_MIX, 0, 700)
+    E = p.E.copy()
+    E[100] = 20
+    p2 = pairgen.Pairs(p.reads, p.refs, p.len, E, p.related, p.k)
+    b = to_device(p2, ctx, per_pair=True, offsets=True, max_E=15)
+    got = results(ctx.filter(b, SS), p.n)
+    with pytest.raises(paf.PafError):
+        ctx.check()
+    assert got[SS][0][100] == 0 and got[SS][1][100] == 0
+    want = oracle_for(p, SS)
+    mask = np.arange(p.n) != 100
+    assert np.array_equal(got[SS][1][mask], want[SS][1][mask])
+    assert np.array_equal(got[SS][0][mask], want[SS][0][mask])
