@@ -228,6 +228,17 @@ paf_status paf_filter_ordered(paf_ctx* ctx, const paf_batch* batch, uint32_t fil
 paf_status paf_filter_bucketed(paf_ctx* ctx, const paf_batch* batch, uint32_t filters,
                                const paf_out* out, void* stream);
 
+/* Step a9, chunk-local bucketing (SneakySnake alone).  The cost model's
+ * prediction puts every pair on one of 16 levels (width 2 obstacles, highest
+ * first).  The compacting filter then sorts the pairs of each of its chunks
+ * by level before the first window, so each pass of 64 takes pairs of like
+ * cost, while the pairs stay in place in memory (no global permutation, no
+ * gathers).  Model and filter are captured in one HIP graph per (batch,
+ * layout, outputs).  Outputs as paf_filter, in the original order.  The
+ * launch layout is the forced or autotuned one if it has chunk_tiles > 0,
+ * else one-wave blocks with 8-tile chunks. */
+paf_status paf_filter_bucketed_local(paf_ctx* ctx, const paf_batch* batch, const paf_out* out, void* stream);
+
 /* Step a11 -- streaming from host memory (the host-to-accelerator stream of
  * Ch. 4, Secs. 4.2-4.4).  All pointers [host]; page-locked (pinned) memory
  * lets the copies overlap the filtering.  Pairs are stored back to back:

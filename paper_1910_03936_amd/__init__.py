@@ -30,7 +30,7 @@ EXPORTS = ("paf_create", "paf_destroy", "paf_last_error", "paf_check", "paf_pack
            "paf_filter", "paf_filter_persistent", "paf_autotune", "paf_set_layout", "paf_features",
            "paf_mlp_set_params", "paf_mlp_get_params", "paf_mlp_forward", "paf_mlp_train_step",
            "paf_mlp_predict", "paf_mlp_train", "paf_bucket", "paf_filter_ordered", "paf_filter_bucketed",
-           "paf_stream_filter")
+           "paf_filter_bucketed_local", "paf_stream_filter")
 
 
 class PafError(RuntimeError):
@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH):
         "paf_mlp_predict": ([P, ctypes.POINTER(_Batch), P, P]),
         "paf_mlp_train": ([P, P, P, U64, U32, U32, ctypes.c_float, P, P]),
         "paf_filter_bucketed": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
+        "paf_filter_bucketed_local": ([P, ctypes.POINTER(_Batch), ctypes.POINTER(_Out), P]),
         "paf_filter_ordered": ([P, ctypes.POINTER(_Batch), U32, P, ctypes.POINTER(_Out), P]),
         "paf_stream_filter": ([P, ctypes.POINTER(_HostBatch), U64, U32, I, ctypes.POINTER(_Out),
                                ctypes.POINTER(_StreamStats)]),
@@ -344,6 +345,12 @@ class Context:
         cb, co = batch.c(), self._out(out)
         _check(self.lib.paf_filter_ordered(self.h, ctypes.byref(cb), filters, _ptr(order), ctypes.byref(co),
                                            _stream(stream)))
+        return out
+
+    def filter_bucketed_local(self, batch: Batch, out: dict | None = None, stream=None) -> dict:
+        out = out or self.alloc_out(batch.n_pairs, SNEAKYSNAKE, batch.device)
+        cb, co = batch.c(), self._out(out)
+        _check(self.lib.paf_filter_bucketed_local(self.h, ctypes.byref(cb), ctypes.byref(co), _stream(stream)))
         return out
 
     def filter_bucketed(self, batch: Batch, filters: int = SNEAKYSNAKE, out: dict | None = None,

@@ -67,6 +67,7 @@ paf_status check_batch(const paf_ctx* ctx, const paf_batch* b, uint32_t filters,
     p.err = ctx->d_err;
     p.grab = 1;
     p.chunk = 0;
+    p.order_key = nullptr;
     return PAF_OK;
 }
 
@@ -165,7 +166,9 @@ paf_status run_graph(paf_ctx* ctx, const paf_ctx::GraphKey& key, hipStream_t str
 // and launched on `stream`.
 paf_status run_persistent(paf_ctx* ctx, FilterParams p, Engine eng, int emax, const paf_layout& L,
                           hipStream_t stream, bool use_graph) {
-    const bool general = true;
+    // Per-pair lengths, thresholds, offsets or an order need the general
+    // kernels; a uniform batch in place takes the plain ones.
+    const bool general = p.len || p.E || p.word_offset || p.perm;
     // SneakySnake alone with a chunk size: the compacting engine; its queue
     // and grid count chunks instead of tiles.
     if (eng == Engine::Snake && L.chunk_tiles > 0) eng = Engine::Chunk;
@@ -237,15 +240,16 @@ paf_status ensure_bucket_ws(paf_ctx* ctx, uint64_t n) {
 }
 
 // Launch layout: the forced one, else the autotuned one for this class, else
-// the default (work queue for the persistent entry point; a full grid of
-// one-wave blocks for orders given by a permutation, where measured
-// dispatch by the hardware beat the queue).
+// the default (work queue for the persistent entry point; for orders given
+// by a permutation, a full grid of one-wave blocks, compacting 8-tile chunks
+// for SneakySnake alone, where measured dispatch by the hardware beat the
+// queue).
 paf_layout layout_for(paf_ctx* ctx, const FilterParams& p, int emax, bool queue_default = true) {
     if (ctx->layout_forced) return ctx->forced;
     auto it = ctx->tuned.find(std::make_tuple((int)p.wmax, emax, p.filters));
     if (it != ctx->tuned.end()) return it->second;
     if (queue_default) return default_layout();
-    return paf_layout{1u, 1u, 0u, 1u, 0u};
+    return paf_layout{1u, 1u, 0u, 1u, 8u};
 }
 
 void set_outputs(FilterParams& p, const paf_out* out) {
@@ -614,6 +618,34 @@ paf_status paf_filter_bucketed(paf_ctx* ctx, const paf_batch* batch, uint32_t fi
                                                   p.max_E, p.n_pairs, out->accept_bits[f], s),
                         "accept bits");
         return PAF_OK;
+    });
+}
+
+paf_status paf_filter_bucketed_local(paf_ctx* ctx, const paf_batch* batch, const paf_out* out, void* stream) {
+    const uint32_t filters = PAF_SNEAKYSNAKE;
+    FilterParams p;
+    paf_status st = check_batch(ctx, batch, filters, p);
+    if (st != PAF_OK) return st;
+    if ((st = check_out(out, filters)) != PAF_OK) return st;
+    if (!ctx->mlp_ready) return fail(PAF_ERR_STATE, "no cost model: call paf_mlp_set_params first");
+    const int emax = emax_bucket((int)p.max_E);
+    if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
+    PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    if ((st = ensure_bucket_ws(ctx, p.n_pairs)) != PAF_OK) return st;
+    set_outputs(p, out);
+    FilterParams q = p;
+    q.order_key = ctx->ws_bucket;
+    paf_layout L = layout_for(ctx, p, emax, false);
+    if (L.chunk_tiles == 0) L = paf_layout{1u, 1u, 0u, 1u, 8u};
+    paf_ctx::GraphKey key{0, 0, 0, 0};
+    const uint64_t* words = reinterpret_cast<const uint64_t*>(&q);
+    for (size_t i = 0; i < sizeof(q) / 8; ++i) key.a = mix(key.a, words[i]);
+    key.b = mix(mix(0x10CA1ull, (uint64_t)emax), (uint64_t)L.waves_per_block);
+    key.c = mix(mix(L.blocks_per_cu, L.tiles_per_grab), L.chunk_tiles);
+    key.d = p.n_pairs;
+    return run_graph(ctx, key, (hipStream_t)stream, [&](hipStream_t s) -> paf_status {
+        PAF_HIP(launch_learned_buckets(ctx->mlp, p, ctx->num_cus, nullptr, ctx->ws_bucket, s, true), "cost model");
+        return run_persistent(ctx, q, Engine::Snake, emax, L, s, false);
     });
 }
 

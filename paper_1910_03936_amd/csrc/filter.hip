@@ -366,6 +366,69 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
     const bool mask_E = GENERAL ? (P.E != nullptr || P.uniform_E < (uint32_t)EMAX)
                                 : (P.uniform_E < (uint32_t)EMAX);
     uint32_t n_ent = n_here;
+    // With a key per pair (the cost model's level), the first window's list
+    // holds the chunk's pairs in ascending key order (a stable counting sort
+    // by wave ballots), so each pass of 64 takes pairs of like cost.
+    const bool keyed = P.order_key != nullptr && plain_out;
+    if (keyed) {
+        // Key of pair i of the chunk (16 = no entry: outside the batch or
+        // outside its bounds), with its length and threshold.
+        auto key_of = [&](uint32_t i, ChunkEntry& t) -> uint32_t {
+            t = ChunkEntry{};
+            t.idx = i;
+            t.m = P.uniform_len;
+            t.E = P.uniform_E;
+            if (i >= n_here) return 16u;
+            const uint64_t slot = slot0 + i;
+            if (GENERAL) {
+                if (P.len) t.m = P.len[slot];
+                if (P.E) t.E = P.E[slot];
+                if (t.m < 1 || t.m > P.max_len || t.E > P.max_E) return 16u;
+            }
+            return P.order_key[slot] & 15u;
+        };
+        uint32_t base[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) base[v] = 0;
+        for (uint32_t g = 0; g < n_here; g += 64) {
+            ChunkEntry t;
+            const uint32_t b = key_of(g + (uint32_t)lane, t);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) base[v] += (uint32_t)__builtin_popcountll(__ballot(b == (uint32_t)v));
+        }
+        uint32_t run = 0;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const uint32_t c = base[v];
+            base[v] = run;
+            run += c;
+        }
+        n_ent = run;
+        for (uint32_t g = 0; g < n_here; g += 64) {
+            const uint32_t i = g + (uint32_t)lane;
+            ChunkEntry t;
+            const uint32_t b = key_of(i, t);
+            if (i < n_here) {
+                const uint64_t slot = slot0 + i;
+                if (b == 16u) {
+                    atomicOr(P.err, 1u);
+                    P.cnt[0][slot] = 0;
+                } else if (GENERAL) {
+                    L.off[i] = P.word_offset ? P.word_offset[slot] : slot * (uint64_t)P.stride_words;
+                }
+            }
+            uint32_t pos = 0;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const uint64_t mv = __ballot(b == (uint32_t)v);
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mv >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mv, 0u));
+                if (b == (uint32_t)v) pos = base[v] + below;
+                base[v] += (uint32_t)__builtin_popcountll(mv);
+            }
+            if (b < 16u) L.ent[pos] = chunk_pack(t);
+        }
+    }
     for (uint32_t w = 0; n_ent > 0; ++w) {
         wave_lds_sync();
         uint32_t n_out = 0;
@@ -375,7 +438,7 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
             ChunkEntry t = {};
             DT dead = 0;
             uint64_t off = 0;
-            if (w == 0) {
+            if (w == 0 && !keyed) {
                 t.idx = i;
                 t.c = 0;
                 t.e = 0;

@@ -34,6 +34,13 @@ typedef __attribute__((ext_vector_type(2))) float f32x2;
 typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 typedef __attribute__((ext_vector_type(2))) short s16x2;
 
+// relu as an integer max on the bit pattern: negative values (sign bit set)
+// become +0, the rest pass unchanged.
+__device__ __forceinline__ float relu_bits(float x) {
+    const int b = __builtin_bit_cast(int, x);
+    return __builtin_bit_cast(float, b > 0 ? b : 0);
+}
+
 // relu of two fp32 values rounded to bf16, as the packed bf16 bit patterns.
 __device__ __forceinline__ s16x2 relu_pk(float a, float b) {
     const bf16x2 h = __builtin_convertvector(f32x2{a, b}, bf16x2);
@@ -99,25 +106,52 @@ __device__ __forceinline__ void count_long(const WindowWords& q, uint32_t* z) {
         constexpr int d = I - EF;
         // m >= 64 + EF: no read position of the first two windows lies past the
         // read, so the only vacant cells are the constant left edge of window 0.
+        // z counts blocked cells here.
         const uint32_t mw = diag_raw<d>(q) | (K == 0 ? left_vacant<d>() : 0u);
-        z[I] += __builtin_popcount(~mw);
+        z[I] += __builtin_popcount(mw);
         count_long<EF, K, I + 1>(q, z);
+    }
+}
+
+// Fraction features of the diagonals inside the pair's own threshold; those
+// beyond it are 0.  `masked` is false when every lane of the wave has E >= EF.
+template <int EF>
+__device__ __forceinline__ void store_fractions(const float* v, uint32_t E, bool masked, float* f) {
+    constexpr int D = 2 * EF + 1;
+    if (EF <= 15 && !masked) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) f[32 + i - EF] = v[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int d = i - EF;
+            const uint32_t ad = (uint32_t)(d < 0 ? -d : d);
+            f[32 + d] = ad <= E ? v[i] : 0.0f;
+        }
     }
 }
 
 template <int EF>
 __device__ __forceinline__ void pair_features(const uint64_t* rd, const uint64_t* rf, uint32_t m,
-                                              uint32_t E, float* f, bool all_long) {
+                                              uint32_t E, float* f, bool all_long, bool masked) {
     constexpr int D = 2 * EF + 1;
     uint32_t z[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) z[i] = 0;
     const int W = (int)((m + 31) >> 5);
+    float v[D];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) f[i] = 0.0f;
+    f[0] = (float)m * (1.0f / 512.0f);
+    f[1] = (float)E * (1.0f / 32.0f);
     // The fast path doubles the feature code; above 15 diagonals per side it
     // would push the fused model kernel past its register budget.
     if (EF <= 15 && all_long) {
         count_long<EF, 0>(window_words_direct(rd, rf, 0, W, (int)m), z);
         count_long<EF, 1>(window_words_direct(rd, rf, 1, W, (int)m), z);
+        // 64 columns: the fraction (64 - blocked) / 64 = 1 - blocked / 64, exact.
+#pragma unroll
+        for (int i = 0; i < D; ++i) v[i] = __builtin_fmaf((float)z[i], -1.0f / 64.0f, 1.0f);
     } else {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -128,19 +162,12 @@ __device__ __forceinline__ void pair_features(const uint64_t* rd, const uint64_t
 #pragma unroll
             for (int i = 0; i < D; ++i) z[i] += __builtin_popcount(~M[i] & colvalid);
         }
-    }
-    const uint32_t cols = m < 64 ? m : 64;
-    const float rcp = 1.0f / (float)cols;
+        const uint32_t cols = m < 64 ? m : 64;
+        const float rcp = 1.0f / (float)cols;
 #pragma unroll
-    for (int i = 0; i < 64; ++i) f[i] = 0.0f;
-    f[0] = (float)m * (1.0f / 512.0f);
-    f[1] = (float)E * (1.0f / 32.0f);
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-        const int d = i - EF;
-        const uint32_t ad = (uint32_t)(d < 0 ? -d : d);
-        f[32 + d] = ad <= E ? (float)z[i] * rcp : 0.0f;
+        for (int i = 0; i < D; ++i) v[i] = (float)z[i] * rcp;
     }
+    store_fractions<EF>(v, E, masked, f);
 }
 
 struct PairRef {
@@ -176,7 +203,7 @@ __global__ void __launch_bounds__(256) features_kernel(FilterParams P, float* ou
     const PairRef r = pair_ref(P, p);
     float f[64];
     if (r.valid) {
-        pair_features<EF>(r.rd, r.rf, r.m, r.E, f, false);
+        pair_features<EF>(r.rd, r.rf, r.m, r.E, f, false, true);
     } else {
 #pragma unroll
         for (int i = 0; i < 64; ++i) f[i] = 0.0f;
@@ -212,6 +239,18 @@ __host__ __device__ __forceinline__ uint32_t cost_bucket(float y, uint32_t m, ui
     return b < 15u ? b : 15u;
 }
 
+// Level of a pair for the compacting filter's in-chunk order: the prediction
+// on 16 levels of width 2 (0..32 obstacles), stored as 15 - level so that
+// ascending order puts the costliest pairs first.  Pairs with similar counts
+// take similar numbers of steps in each window, which is what makes a window
+// pass of the compacting engine long.
+__host__ __device__ __forceinline__ uint32_t chunk_level(float y) {
+    float yc = y > 0.0f ? y : 0.0f;   // NaN -> 0
+    yc = yc < 32.0f ? yc : 32.0f;
+    const uint32_t l = (uint32_t)floorf(yc * 0.5f);
+    return l < 15u ? l : 15u;
+}
+
 // ---------------------------------------------------------------------------
 // Fused inference: features -> layer 1 -> layer 2 -> head -> bucket, one
 // 64-pair tile per wave; weights stay in LDS for the whole (persistent) launch.
@@ -223,6 +262,7 @@ struct KeyParams {
     const float* w3r;
     float* pred;       // optional
     uint8_t* bucket;   // optional
+    uint32_t chunk_key;  // bucket = 15 - chunk_level (in-chunk order) instead of 15 - cost_bucket
 };
 
 constexpr int kKeyWaves = 8;  // waves per block of the fused kernel (weights shared in LDS)
@@ -251,10 +291,11 @@ __device__ __forceinline__ FeatWords feat_words(const FilterParams& P, uint64_t 
 }
 
 template <int EF>
-__device__ __forceinline__ void features_from_words(const FeatWords& w, float* f, bool all_long) {
+__device__ __forceinline__ void features_from_words(const FeatWords& w, float* f, bool all_long,
+                                                    bool masked) {
     uint64_t rd[3] = {w.r0, w.r1, w.r2};
     uint64_t rf[2] = {w.f0, w.f1};
-    pair_features<EF>(rd, rf, w.m, w.E, f, all_long);
+    pair_features<EF>(rd, rf, w.m, w.E, f, all_long, masked);
 }
 
 template <int EF>
@@ -287,8 +328,9 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
         {
             float f[64];
             const bool all_long = !wave_any(cur.valid && cur.m < 64u + EF);
+            const bool masked = wave_any(cur.valid && cur.E < (uint32_t)EF);
             if (cur.valid) {
-                features_from_words<EF>(cur, f, all_long);
+                features_from_words<EF>(cur, f, all_long, masked);
             } else {
 #pragma unroll
                 for (int i = 0; i < 64; ++i) f[i] = 0.0f;
@@ -372,7 +414,7 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
 #pragma unroll
             for (int mt2 = 0; mt2 < 8; ++mt2)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) t += sW3[16 * mt2 + 4 * grp + i] * fmaxf(acc2[mt2][nt][i], 0.0f);
+                for (int i = 0; i < 4; ++i) t += sW3[16 * mt2 + 4 * grp + i] * relu_bits(acc2[mt2][nt][i]);
             t += __shfl_xor(t, 16);
             t += __shfl_xor(t, 32);
             if (grp == nt) yv = t;
@@ -380,7 +422,10 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
         const float y = yv + b3;
         if (p < P.n_pairs) {
             if (K.pred) K.pred[p] = valid ? y : 0.0f;
-            if (K.bucket) K.bucket[p] = (uint8_t)(valid ? 15u - cost_bucket(y, m, E, P.max_len, P.max_E) : 15u);
+            if (K.bucket) {
+                const uint32_t lv = K.chunk_key ? chunk_level(y) : cost_bucket(y, m, E, P.max_len, P.max_E);
+                K.bucket[p] = (uint8_t)(valid ? 15u - lv : 15u);
+            }
         }
         wave_lds_sync();
     }
@@ -751,7 +796,7 @@ void mlp_free(MlpDev& m) {
 size_t bucket_count_words(uint64_t n) { return 16 * ((n + kBucketChunk - 1) / kBucketChunk); }
 
 hipError_t launch_learned_buckets(const MlpDev& m, const FilterParams& p, int num_cus, float* pred,
-                                  uint8_t* bucket, hipStream_t s) {
+                                  uint8_t* bucket, hipStream_t s, bool chunk_key) {
     const int emax = emax_bucket((int)p.max_E);
     if (emax < 0) return hipErrorInvalidValue;
     const void* k = feature_kernel_for(feature_ef(emax), true);
@@ -764,6 +809,7 @@ hipError_t launch_learned_buckets(const MlpDev& m, const FilterParams& p, int nu
     kp.w3r = m.w3r;
     kp.pred = pred;
     kp.bucket = bucket;
+    kp.chunk_key = chunk_key ? 1u : 0u;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64 * kKeyWaves, 0) != hipSuccess || nb < 1) nb = 1;
     const uint32_t want = (uint32_t)(num_cus * nb);

@@ -39,6 +39,8 @@ struct FilterParams {
     uint32_t* queue;        // tile counter of the persistent launch, or NULL
     uint32_t grab;          // tiles per queue access
     uint32_t chunk;         // tiles per wave-owned chunk (compacting engine)
+    const uint8_t* order_key;  // compacting engine: per-pair key (original order); each chunk's
+                               // pairs enter the first window in ascending key order, or NULL
 };
 
 // Kernel selection.
@@ -97,7 +99,8 @@ struct MlpDev {
 };
 size_t bucket_count_words(uint64_t n);
 hipError_t launch_learned_buckets(const MlpDev& m, const FilterParams& p, int num_cus, float* pred,
-                                  uint8_t* bucket, hipStream_t s);
+                                  uint8_t* bucket, hipStream_t s,
+                                  bool chunk_key = false);
 hipError_t launch_bucket_from_pred(const FilterParams& p, const float* pred, uint8_t* bucket, hipStream_t s);
 hipError_t launch_bucket_sort(const uint8_t* bucket, uint64_t n, uint32_t* counts, uint32_t* perm,
                               uint32_t* hist, hipStream_t s);

@@ -273,3 +273,58 @@ def test_bucketed_filter_equals_plain(gpu_ctx, filters):
             assert np.array_equal(acc, want[f][0])
             assert np.array_equal(paf.counts_u16(buck[f][1]).cpu().numpy(), want[f][1].astype(np.int64))
     gpu_ctx.check()
+
+
+@gpu
+def test_bucketed_local_equals_plain(gpu_ctx):
+    """Chunk-local bucketing (model levels order each compacting chunk):
+    identical decisions to the plain filter and the oracle, on uniform and
+    per-pair layouts, ragged batches, graph replays and several layouts."""
+    import paper_1910_03936_amd as paf
+    SS = paf.SNEAKYSNAKE
+    for seed in (10, 11):
+        _set_random_model(gpu_ctx, seed=seed)
+        for w, n in ((pairgen.UNEVEN_MIX, 20_001), (pairgen.FIXED_250BP, 9_000), (pairgen.FIXED_250BP, 65)):
+            b = _workload_batch(gpu_ctx, w, n)
+            p = pairgen.generate(w, 0, n)
+            want = oracle.filter_batch(p.reads, p.refs, p.len, p.E, SS)[SS]
+            for lay in (None, {"lanes_per_pair": 1, "waves_per_block": 4, "blocks_per_cu": 2,
+                               "tiles_per_grab": 1, "chunk_tiles": 3},
+                        {"lanes_per_pair": 1, "waves_per_block": 2, "blocks_per_cu": 0,
+                         "tiles_per_grab": 1, "chunk_tiles": 16}):
+                gpu_ctx.set_layout(lay)
+                try:
+                    for rep in range(2):   # capture, then replay
+                        got = gpu_ctx.filter_bucketed_local(b)
+                        acc = paf.accept_bits_to_bool(got[SS][0], n).cpu().numpy().astype(np.uint8)
+                        assert np.array_equal(acc, want[0]), (w.name, n, lay, rep)
+                        assert np.array_equal(paf.counts_u16(got[SS][1]).cpu().numpy(),
+                                              want[1].astype(np.int64)), (w.name, n, lay, rep)
+                finally:
+                    gpu_ctx.set_layout(None)
+    gpu_ctx.check()
+
+
+@gpu
+def test_bucketed_local_range_violation(gpu_ctx):
+    import paper_1910_03936_amd as paf
+    SS = paf.SNEAKYSNAKE
+    _set_random_model(gpu_ctx, seed=12)
+    p = pairgen.generate(pairgen.UNEVEN_MIX, 0, 1000)
+    E = p.E.copy()
+    E[333] = 20
+    dev = torch.device("cuda", 0)
+    b = gpu_ctx.pack_pairs(torch.from_numpy(p.reads).to(dev), torch.from_numpy(p.refs).to(dev),
+                           lens=torch.from_numpy(p.len.astype(np.int16)).to(dev),
+                           Es=torch.from_numpy(E).to(dev), max_len=int(p.len.max()), max_E=15, offsets=True)
+    got = gpu_ctx.filter_bucketed_local(b)
+    torch.cuda.synchronize()
+    with pytest.raises(paf.PafError):
+        gpu_ctx.check()
+    acc = paf.accept_bits_to_bool(got[SS][0], p.n).cpu().numpy()
+    cnt = paf.counts_u16(got[SS][1]).cpu().numpy()
+    assert acc[333] == 0 and cnt[333] == 0
+    want = oracle.filter_batch(p.reads, p.refs, p.len, p.E, SS)[SS]
+    mask = np.arange(p.n) != 333
+    assert np.array_equal(cnt[mask], want[1][mask].astype(np.int64))
+    assert np.array_equal(acc[mask].astype(np.uint8), want[0][mask])
