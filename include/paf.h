@@ -122,9 +122,10 @@ paf_status paf_pack_host(const uint8_t* codes, uint32_t code_stride, const uint1
  * fast path plus amended shifted masks (Ch. 5, Sec. 5.2) and Shouji's
  * sliding-window search (Ch. 6, Sec. 6.2).  filters: mask of PAF_* bits.
  * SneakySnake alone runs on the compacting engine (see paf_layout's
- * chunk_tiles; 8 tiles per chunk, 4 waves per block unless a layout was
- * forced with paf_set_layout, whose waves_per_block and chunk_tiles then
- * apply here too; chunk_tiles = 0 selects the per-tile engine). */
+ * chunk_tiles; 6 tiles per chunk, 2 waves per block, passes of 2 windows
+ * unless a layout was forced with paf_set_layout, whose waves_per_block,
+ * chunk_tiles and pass widths then apply here too; chunk_tiles = 0 selects
+ * the per-tile engine). */
 paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, const paf_out* out,
                       void* stream);
 
@@ -149,6 +150,9 @@ typedef struct {
                                   all are decided; K in 1..16 = a wave owns K tiles and, after
                                   each 32-column window, regroups the pairs still undecided
                                   into full waves (the queue then hands out chunks) */
+    uint32_t first_pass_windows;   /* compacting engine: windows the lanes walk together
+                                      before the first regrouping (0 = 1), 1..16 */
+    uint32_t pass_windows;         /* ... and between later regroupings (0 = 1), 1..16 */
 } paf_layout;
 
 /* Times each candidate layout on `batch` (synchronously, on `stream`),
@@ -228,6 +232,20 @@ paf_status paf_filter_ordered(paf_ctx* ctx, const paf_batch* batch, uint32_t fil
 paf_status paf_filter_bucketed(paf_ctx* ctx, const paf_batch* batch, uint32_t filters,
                                const paf_out* out, void* stream);
 
+/* Step a9, chunk-local bucketing, stage 1: features and cost model of every
+ * pair; key[p] = 15 - level, level = min(15, floor(clamp(y, 0, 32) / 2)),
+ * y the predicted SneakySnake count at E = 31 (key: uint8 [device],
+ * n_pairs entries, original order). */
+paf_status paf_cost_levels(paf_ctx* ctx, const paf_batch* batch, uint8_t* key, void* stream);
+
+/* Stage 2: SneakySnake alone on the compacting engine, the pairs of each
+ * chunk entering its first window in ascending key order (key: uint8 per
+ * pair [device], original order, used modulo 16).  Any key gives the
+ * outputs of paf_filter; a key that groups pairs of like cost makes the
+ * launch faster.  Layout as paf_filter_bucketed_local. */
+paf_status paf_filter_keyed(paf_ctx* ctx, const paf_batch* batch, const uint8_t* key, const paf_out* out,
+                            void* stream);
+
 /* Step a9, chunk-local bucketing (SneakySnake alone).  The cost model's
  * prediction puts every pair on one of 16 levels (width 2 obstacles, highest
  * first).  The compacting filter then sorts the pairs of each of its chunks
@@ -236,7 +254,7 @@ paf_status paf_filter_bucketed(paf_ctx* ctx, const paf_batch* batch, uint32_t fi
  * gathers).  Model and filter are captured in one HIP graph per (batch,
  * layout, outputs).  Outputs as paf_filter, in the original order.  The
  * launch layout is the forced or autotuned one if it has chunk_tiles > 0,
- * else one-wave blocks with 8-tile chunks. */
+ * else paf_filter's. */
 paf_status paf_filter_bucketed_local(paf_ctx* ctx, const paf_batch* batch, const paf_out* out, void* stream);
 
 /* Step a11 -- streaming from host memory (the host-to-accelerator stream of

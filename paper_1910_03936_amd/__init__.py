@@ -30,7 +30,7 @@ EXPORTS = ("paf_create", "paf_destroy", "paf_last_error", "paf_check", "paf_pack
            "paf_filter", "paf_filter_persistent", "paf_autotune", "paf_set_layout", "paf_features",
            "paf_mlp_set_params", "paf_mlp_get_params", "paf_mlp_forward", "paf_mlp_train_step",
            "paf_mlp_predict", "paf_mlp_train", "paf_bucket", "paf_filter_ordered", "paf_filter_bucketed",
-           "paf_filter_bucketed_local", "paf_stream_filter")
+           "paf_filter_bucketed_local", "paf_cost_levels", "paf_filter_keyed", "paf_stream_filter")
 
 
 class PafError(RuntimeError):
@@ -65,7 +65,8 @@ class _StreamStats(ctypes.Structure):
 class Layout(ctypes.Structure):
     _fields_ = [("lanes_per_pair", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
                 ("blocks_per_cu", ctypes.c_uint32), ("tiles_per_grab", ctypes.c_uint32),
-                ("chunk_tiles", ctypes.c_uint32)]
+                ("chunk_tiles", ctypes.c_uint32), ("first_pass_windows", ctypes.c_uint32),
+                ("pass_windows", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -106,6 +107,8 @@ def load_library(path: str = LIB_PATH):
         "paf_mlp_train": ([P, P, P, U64, U32, U32, ctypes.c_float, P, P]),
         "paf_filter_bucketed": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
         "paf_filter_bucketed_local": ([P, ctypes.POINTER(_Batch), ctypes.POINTER(_Out), P]),
+        "paf_cost_levels": ([P, ctypes.POINTER(_Batch), P, P]),
+        "paf_filter_keyed": ([P, ctypes.POINTER(_Batch), P, ctypes.POINTER(_Out), P]),
         "paf_filter_ordered": ([P, ctypes.POINTER(_Batch), U32, P, ctypes.POINTER(_Out), P]),
         "paf_stream_filter": ([P, ctypes.POINTER(_HostBatch), U64, U32, I, ctypes.POINTER(_Out),
                                ctypes.POINTER(_StreamStats)]),
@@ -345,6 +348,19 @@ class Context:
         cb, co = batch.c(), self._out(out)
         _check(self.lib.paf_filter_ordered(self.h, ctypes.byref(cb), filters, _ptr(order), ctypes.byref(co),
                                            _stream(stream)))
+        return out
+
+    def cost_levels(self, batch: Batch, stream=None) -> torch.Tensor:
+        """uint8 key per pair: 15 - the model's cost level (chunk-local order)."""
+        key = torch.empty(batch.n_pairs, dtype=torch.uint8, device=batch.device)
+        cb = batch.c()
+        _check(self.lib.paf_cost_levels(self.h, ctypes.byref(cb), _ptr(key), _stream(stream)))
+        return key
+
+    def filter_keyed(self, batch: Batch, key: torch.Tensor, out: dict | None = None, stream=None) -> dict:
+        out = out or self.alloc_out(batch.n_pairs, SNEAKYSNAKE, batch.device)
+        cb, co = batch.c(), self._out(out)
+        _check(self.lib.paf_filter_keyed(self.h, ctypes.byref(cb), _ptr(key), ctypes.byref(co), _stream(stream)))
         return out
 
     def filter_bucketed_local(self, batch: Batch, out: dict | None = None, stream=None) -> dict:

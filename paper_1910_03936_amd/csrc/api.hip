@@ -67,6 +67,7 @@ paf_status check_batch(const paf_ctx* ctx, const paf_batch* b, uint32_t filters,
     p.err = ctx->d_err;
     p.grab = 1;
     p.chunk = 0;
+    p.span0 = p.span = 1;
     p.order_key = nullptr;
     return PAF_OK;
 }
@@ -108,14 +109,15 @@ paf_layout default_layout() {
 }
 
 // Launch shape of paf_filter's SneakySnake-only launch.
-paf_layout plain_layout() { return paf_layout{1u, 4u, 0u, 1u, 8u}; }
+paf_layout plain_layout() { return paf_layout{1u, 2u, 0u, 1u, 6u, 2u, 2u}; }
 
 bool layout_ok(const paf_layout& l) {
     return l.lanes_per_pair == 1 &&
            (l.waves_per_block == 1 || l.waves_per_block == 2 || l.waves_per_block == 4 ||
             l.waves_per_block == 8) &&
            l.blocks_per_cu <= 64 && l.tiles_per_grab >= 1 &&
-           l.tiles_per_grab <= 64 && l.chunk_tiles <= 16;
+           l.tiles_per_grab <= 64 && l.chunk_tiles <= 16 && l.first_pass_windows <= 16 &&
+           l.pass_windows <= 16;
 }
 
 // Largest resident block count per CU for this kernel and LDS size.
@@ -178,6 +180,8 @@ paf_status run_persistent(paf_ctx* ctx, FilterParams p, Engine eng, int emax, co
     LaunchShape sh;
     sh.waves_per_block = L.waves_per_block;
     p.chunk = eng == Engine::Chunk ? L.chunk_tiles : 0u;
+    p.span0 = std::max(1u, L.first_pass_windows);
+    p.span = std::max(1u, L.pass_windows);
     sh.lds_bytes = eng == Engine::Chunk ? chunk_lds_bytes(L.waves_per_block, general, emax, L.chunk_tiles)
                                         : filter_lds_bytes(L.waves_per_block, p.wmax);
     if (sh.lds_bytes > 160 * 1024) return fail(PAF_ERR_RANGE, "layout needs more LDS than a CU has");
@@ -249,7 +253,7 @@ paf_layout layout_for(paf_ctx* ctx, const FilterParams& p, int emax, bool queue_
     auto it = ctx->tuned.find(std::make_tuple((int)p.wmax, emax, p.filters));
     if (it != ctx->tuned.end()) return it->second;
     if (queue_default) return default_layout();
-    return paf_layout{1u, 1u, 0u, 1u, 8u};
+    return paf_layout{1u, 2u, 0u, 1u, 6u, 2u, 2u};
 }
 
 void set_outputs(FilterParams& p, const paf_out* out) {
@@ -409,6 +413,8 @@ paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, co
     if (eng == Engine::Snake && PL.chunk_tiles > 0) {
         eng = Engine::Chunk;
         p.chunk = PL.chunk_tiles;
+        p.span0 = std::max(1u, PL.first_pass_windows);
+        p.span = std::max(1u, PL.pass_windows);
         sh.waves_per_block = PL.waves_per_block;
         sh.lds_bytes = chunk_lds_bytes(sh.waves_per_block, general, emax, p.chunk);
         if (sh.lds_bytes > 160 * 1024) return fail(PAF_ERR_RANGE, "layout needs more LDS than a CU has");
@@ -471,13 +477,15 @@ paf_status paf_autotune(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, 
                 cands.push_back(l);
             }
         if (eng != Engine::Snake) continue;
-        for (uint32_t K : {4u, 8u, 16u}) {
+        for (uint32_t K : {4u, 6u, 8u, 16u}) {
             const size_t lds = chunk_lds_bytes(wpb, true, emax, K);
             if (lds > 160 * 1024) continue;
-            cands.push_back(paf_layout{1u, wpb, 0u, 1u, K});
-            for (uint32_t bpc : {1u, 2u, 4u}) {
-                if (lds * bpc > 160 * 1024 || wpb * bpc > 32) continue;
-                cands.push_back(paf_layout{1u, wpb, bpc, 1u, K});
+            for (uint32_t sp : {1u, 2u}) {
+                cands.push_back(paf_layout{1u, wpb, 0u, 1u, K, sp, sp});
+                for (uint32_t bpc : {2u, 4u}) {
+                    if (lds * bpc > 160 * 1024 || wpb * bpc > 32) continue;
+                    cands.push_back(paf_layout{1u, wpb, bpc, 1u, K, sp, sp});
+                }
             }
         }
     }
@@ -621,6 +629,42 @@ paf_status paf_filter_bucketed(paf_ctx* ctx, const paf_batch* batch, uint32_t fi
     });
 }
 
+paf_status paf_cost_levels(paf_ctx* ctx, const paf_batch* batch, uint8_t* key, void* stream) {
+    FilterParams p;
+    paf_status st = check_batch(ctx, batch, PAF_SNEAKYSNAKE, p);
+    if (st != PAF_OK) return st;
+    if (!key) return fail(PAF_ERR_ARG, "key is NULL");
+    if (!ctx->mlp_ready) return fail(PAF_ERR_STATE, "no cost model: call paf_mlp_set_params first");
+    PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    PAF_HIP(launch_learned_buckets(ctx->mlp, p, ctx->num_cus, nullptr, key, (hipStream_t)stream, true),
+            "cost model launch");
+    return PAF_OK;
+}
+
+// Layout of the keyed compacting launch: the forced or tuned one if it
+// compacts, else one-wave blocks with 8-tile chunks.
+paf_layout keyed_layout(paf_ctx* ctx, const FilterParams& p, int emax) {
+    paf_layout L = layout_for(ctx, p, emax, false);
+    if (L.chunk_tiles == 0) L = paf_layout{1u, 2u, 0u, 1u, 6u, 2u, 2u};
+    return L;
+}
+
+paf_status paf_filter_keyed(paf_ctx* ctx, const paf_batch* batch, const uint8_t* key, const paf_out* out,
+                            void* stream) {
+    const uint32_t filters = PAF_SNEAKYSNAKE;
+    FilterParams p;
+    paf_status st = check_batch(ctx, batch, filters, p);
+    if (st != PAF_OK) return st;
+    if ((st = check_out(out, filters)) != PAF_OK) return st;
+    if (!key) return fail(PAF_ERR_ARG, "key is NULL");
+    const int emax = emax_bucket((int)p.max_E);
+    if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
+    PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    set_outputs(p, out);
+    p.order_key = key;
+    return run_persistent(ctx, p, Engine::Snake, emax, keyed_layout(ctx, p, emax), (hipStream_t)stream, true);
+}
+
 paf_status paf_filter_bucketed_local(paf_ctx* ctx, const paf_batch* batch, const paf_out* out, void* stream) {
     const uint32_t filters = PAF_SNEAKYSNAKE;
     FilterParams p;
@@ -635,8 +679,7 @@ paf_status paf_filter_bucketed_local(paf_ctx* ctx, const paf_batch* batch, const
     set_outputs(p, out);
     FilterParams q = p;
     q.order_key = ctx->ws_bucket;
-    paf_layout L = layout_for(ctx, p, emax, false);
-    if (L.chunk_tiles == 0) L = paf_layout{1u, 1u, 0u, 1u, 8u};
+    const paf_layout L = keyed_layout(ctx, p, emax);
     paf_ctx::GraphKey key{0, 0, 0, 0};
     const uint64_t* words = reinterpret_cast<const uint64_t*>(&q);
     for (size_t i = 0; i < sizeof(q) / 8; ++i) key.a = mix(key.a, words[i]);

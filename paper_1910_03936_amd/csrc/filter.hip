@@ -344,6 +344,53 @@ __device__ __forceinline__ ChunkEntry chunk_unpack(uint64_t v) {
     return t;
 }
 
+// Match words of one window for the compacting engine: bit j of Z_d is 1
+// when column j is a free cell of diagonal d, i.e. the complement of the
+// mismatch word (lo ^ flo) | (hi ^ fhi) over the two code planes.  VAC folds
+// in the vacant cells (first and last windows), CONT the dead-diagonal bit of
+// a snake that entered inside a pipe (bit 0 of the window).  v_bitop3 takes
+// s1 | (s0 ^ s2) (truth table 0xDE) and its complement (0x21) in one
+// instruction; both are symmetric in s0 and s2.
+__device__ __forceinline__ uint32_t or_xor3(uint32_t a, uint32_t t, uint32_t b) {
+    return __builtin_amdgcn_bitop3_b32(a, t, b, 0xDE);
+}
+__device__ __forceinline__ uint32_t nor_xor3(uint32_t a, uint32_t t, uint32_t b) {
+    return __builtin_amdgcn_bitop3_b32(a, t, b, 0x21);
+}
+// acc | (z & ~y) in one instruction (truth table 0xF4 with s0 = acc).
+__device__ __forceinline__ uint32_t or_andn(uint32_t acc, uint32_t z, uint32_t y) {
+    return __builtin_amdgcn_bitop3_b32(acc, z, y, 0xF4);
+}
+
+template <int EMAX, bool VAC, bool CONT, typename DT, int I = 0>
+__device__ __forceinline__ void chunk_map(const WindowWords& q, DT dead, uint32_t* M) {
+    if constexpr (I < 2 * EMAX + 1) {
+        constexpr int d = I - EMAX;
+        uint32_t lo, hi;
+        if constexpr (d > 0) {
+            lo = funnel(q.nlo, q.clo, d);
+            hi = funnel(q.nhi, q.chi, d);
+        } else if constexpr (d == 0) {
+            lo = q.clo;
+            hi = q.chi;
+        } else {
+            lo = funnel(q.clo, q.plo, 32 + d);
+            hi = funnel(q.chi, q.phi, 32 + d);
+        }
+        uint32_t t;
+        if constexpr (VAC || CONT) {
+            uint32_t v = 0;
+            if constexpr (VAC) v = diag_vacant<d>(q);
+            if constexpr (CONT) v |= (uint32_t)((dead >> I) & 1u);
+            t = or_xor3(lo, v, q.flo);
+        } else {
+            t = lo ^ q.flo;
+        }
+        M[I] = nor_xor3(hi, t, q.fhi);
+        chunk_map<EMAX, VAC, CONT, DT, I + 1>(q, dead, M);
+    }
+}
+
 template <int EMAX, bool GENERAL>
 struct ChunkLds {
     using DT = typename DeadMask<EMAX>::T;
@@ -429,7 +476,9 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
             if (b < 16u) L.ent[pos] = chunk_pack(t);
         }
     }
-    for (uint32_t w = 0; n_ent > 0; ++w) {
+    // Each pass walks windows [w, w + span) with the same lanes; the pairs
+    // still undecided after it are regrouped for the next pass.
+    for (uint32_t w = 0, span = P.span0; n_ent > 0; w += span, span = P.span) {
         wave_lds_sync();
         uint32_t n_out = 0;
         for (uint32_t g = 0; g < n_ent; g += 64) {
@@ -464,71 +513,102 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                 }
             } else if (act) {
                 t = chunk_unpack(L.ent[i]);
-                dead = L.dead[i];
+                dead = t.cont ? L.dead[i] : (DT)0;
                 off = GENERAL ? L.off[t.idx] : (slot0 + t.idx) * (uint64_t)P.stride_words;
             }
             const uint32_t m = act ? t.m : 0u;
             const uint32_t E = t.E;
+            const int W = (int)((m + 31) >> 5);
             uint32_t c = t.c, e = t.e;
-            const WindowWords q = window_words_direct(P.reads + off, P.refs + off, (int)w,
-                                                      (int)((m + 31) >> 5), (int)m);
-            const bool boundary = wave_any(act && (w == 0 || 32u * (w + 2) > m));
-            uint32_t M[D];
-            build_snake_map<EMAX>(q, boundary, M);
-            if (wave_any(act && t.cont)) {
-                // A snake that entered inside a pipe: diagonals whose pipes
-                // ended before this window hit an obstacle in its first column.
-#pragma unroll
-                for (int d = 0; d < D; ++d) M[d] |= t.cont ? (uint32_t)((dead >> d) & 1u) : 0u;
-            }
-            if (mask_E) {
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    const int dd = d - EMAX;
-                    if ((uint32_t)(dd < 0 ? -dd : dd) > E) M[d] = ~0u;
-                }
-            }
-            const uint32_t w0 = 32u * w, wend = w0 + 32u;
-            bool acc = false, ncont = false;
-            uint32_t s_prev = 0;
-            bool inw = act && c < wend;
-            while (inw) {
-                const uint32_t s = c - w0;
-                uint32_t best = 0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) best = max(best, ffbl(M[d] >> s));
-                const bool clear = best == 0xFFFFFFFFu;
-                const uint32_t R = clear ? wend : c + best;
-                const bool reach = R >= m;
-                const bool obst = !reach && !clear;
-                e += obst ? 1u : 0u;
-                c = reach ? c : (clear ? wend : R + 1u);
-                const bool rej = e > E;
-                const bool fin_acc = reach || (obst && !rej && c >= m);
-                acc = fin_acc;
-                if (clear && !reach) {
-                    ncont = true;
-                    s_prev = s;
-                }
-                act = !(fin_acc || rej);
-                inw = act && c < wend;
-            }
-            const bool fin = (i < n_ent) && !act && m != 0u;
-            if (fin) {
-                const uint64_t slot = slot0 + t.idx;
-                if (plain_out) {
-                    P.cnt[0][slot] = (uint16_t)e;
-                    if (acc) atomicOr(&L.acc[t.idx >> 5], 1u << (t.idx & 31u));
+            bool cont = t.cont, acc = false;
+            for (uint32_t wk = w; wk < w + span && wave_any(act); ++wk) {
+                const WindowWords q = window_words_direct(P.reads + off, P.refs + off, (int)wk, W, (int)m);
+                // Vacant cells only occur in the first window and near the end.
+                // A snake that entered inside a pipe sees the diagonals whose
+                // pipes ended before this window blocked in its first column.
+                const bool vac = wave_any(act && (wk == 0 || 32u * (wk + 2) > m));
+                const bool cnt = wave_any(act && cont);
+                uint32_t M[D];
+                if (vac) {
+                    if (cnt) chunk_map<EMAX, true, true>(q, dead, M);
+                    else chunk_map<EMAX, true, false>(q, dead, M);
                 } else {
-                    P.cnt[0][P.perm[slot]] = (uint16_t)e;
+                    if (cnt) chunk_map<EMAX, false, true>(q, dead, M);
+                    else chunk_map<EMAX, false, false>(q, dead, M);
                 }
-            }
-            // Survivors go on to the next window.
-            DT dm = 0;
-            if (wave_any(act && ncont)) {
+                if (mask_E) {
 #pragma unroll
-                for (int d = 0; d < D; ++d) dm |= (DT)min(M[d] >> s_prev, 1u) << d;
+                    for (int d = 0; d < D; ++d) {
+                        const int dd = d - EMAX;
+                        if ((uint32_t)(dd < 0 ? -dd : dd) > E) M[d] = 0u;
+                    }
+                }
+                const uint32_t w0 = 32u * wk, wend = w0 + 32u;
+                const bool live = act;
+                bool ncont = false;
+                uint32_t s_prev = 0;
+                bool inw = act && c < wend;
+                while (inw) {
+                    // Pipes from column c: adding 1 << s to a match word
+                    // carries through its run of free cells from s, so
+                    // Z & ~(Z + (1 << s)) is that run; the OR over the
+                    // diagonals is [s, s + deepest run), with bit 31 set when a
+                    // pipe reaches the window's end.
+                    const uint32_t s = c - w0;
+                    const uint32_t bs = 1u << s;
+                    uint32_t r0 = 0, r1 = 0;
+#pragma unroll
+                    for (int d = 0; d < D; d += 2) {
+                        r0 = or_andn(r0, M[d], M[d] + bs);
+                        if (d + 1 < D) r1 = or_andn(r1, M[d + 1], M[d + 1] + bs);
+                    }
+                    const uint32_t runs = r0 | r1;
+                    const bool clear = (int32_t)runs < 0;
+                    const uint32_t R = clear ? wend : c + (uint32_t)__builtin_popcount(runs);
+                    const bool reach = R >= m;
+                    const bool obst = !reach && !clear;
+                    e += obst ? 1u : 0u;
+                    c = reach ? c : (clear ? wend : R + 1u);
+                    const bool rej = e > E;
+                    const bool fin_acc = reach || (obst && !rej && c >= m);
+                    acc = fin_acc;
+                    if (clear && !reach) {
+                        ncont = true;
+                        s_prev = s;
+                    }
+                    act = !(fin_acc || rej);
+                    inw = act && c < wend;
+                }
+                if (live && !act) {
+                    const uint64_t slot = slot0 + t.idx;
+                    if (plain_out) {
+                        P.cnt[0][slot] = (uint16_t)e;
+                        if (acc) atomicOr(&L.acc[t.idx >> 5], 1u << (t.idx & 31u));
+                    } else {
+                        P.cnt[0][P.perm[slot]] = (uint16_t)e;
+                    }
+                }
+                // A diagonal stays alive into the next window when its run
+                // from s_prev reaches this window's end, i.e. when adding
+                // 1 << s_prev to its match word carries out of bit 31.
+                DT dm = 0;
+                if (wave_any(act && ncont)) {
+                    const uint32_t bs = 1u << s_prev;
+                    uint32_t lo = 0, hi = 0;
+#pragma unroll
+                    for (int d = D - 1; d >= 0; --d) {
+                        const uint32_t carry = (uint32_t)(((uint64_t)M[d] + bs) >> 32);
+                        if (d >= 32) hi = (hi << 1) | carry;
+                        else lo = (lo << 1) | carry;
+                    }
+                    const DT alive = (DT)lo | (sizeof(DT) > 4 ? (DT)((uint64_t)hi << 32) : (DT)0);
+                    constexpr DT all = (D >= 8 * (int)sizeof(DT)) ? ~(DT)0 : (((DT)1 << D) - 1);
+                    dm = ~alive & all;
+                }
+                cont = act && ncont;
+                dead = cont ? dm : (DT)0;
             }
+            // Survivors go on to the next pass.
             const uint64_t bal = __ballot(act);
             const uint32_t pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
@@ -536,9 +616,9 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                 ChunkEntry u = t;
                 u.c = c;
                 u.e = e;
-                u.cont = ncont;
+                u.cont = cont;
                 L.ent[n_out + pre] = chunk_pack(u);
-                L.dead[n_out + pre] = ncont ? dm : (DT)0;
+                L.dead[n_out + pre] = dead;
             }
             n_out += (uint32_t)__builtin_popcountll(bal);
         }

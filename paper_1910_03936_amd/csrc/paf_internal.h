@@ -39,6 +39,7 @@ struct FilterParams {
     uint32_t* queue;        // tile counter of the persistent launch, or NULL
     uint32_t grab;          // tiles per queue access
     uint32_t chunk;         // tiles per wave-owned chunk (compacting engine)
+    uint32_t span0, span;   // compacting engine: windows of the first pass and of later passes
     const uint8_t* order_key;  // compacting engine: per-pair key (original order); each chunk's
                                // pairs enter the first window in ascending key order, or NULL
 };

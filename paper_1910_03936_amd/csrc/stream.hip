@@ -216,7 +216,9 @@ paf_status paf_stream_filter(paf_ctx* ctx, const paf_host_batch* hb, uint64_t ch
             o.accept_bits[f] = s.acc[f];
             o.count[f] = s.cnt[f];
         }
-        st = learned ? paf_filter_bucketed(ctx, &b, filters, &o, comp) : paf_filter(ctx, &b, filters, &o, comp);
+        st = !learned ? paf_filter(ctx, &b, filters, &o, comp)
+             : filters == PAF_SNEAKYSNAKE ? paf_filter_bucketed_local(ctx, &b, &o, comp)
+                                          : paf_filter_bucketed(ctx, &b, filters, &o, comp);
         if (st != PAF_OK) break;
         ok = hipEventRecord(s.computed, comp) == hipSuccess && hipStreamWaitEvent(copy, s.computed, 0) == hipSuccess;
         for (int f = 0; f < 3 && ok; ++f)

@@ -16,9 +16,9 @@ pytestmark = pytest.mark.gpu
 SS = paf.SNEAKYSNAKE
 
 
-def _layout(wpb, bpc, K):
+def _layout(wpb, bpc, K, span0=1, span=1):
     return {"lanes_per_pair": 1, "waves_per_block": wpb, "blocks_per_cu": bpc, "tiles_per_grab": 1,
-            "chunk_tiles": K}
+            "chunk_tiles": K, "first_pass_windows": span0, "pass_windows": span}
 
 
 @pytest.fixture
@@ -33,12 +33,13 @@ def test_chunk_fixed_250bp(ctx, E):
     p = pairgen.generate(w, 17, 64 * 37 + 5)
     want = oracle_for(p, SS)
     b = to_device(p, ctx, per_pair=False, offsets=False)
-    for wpb, K in ((4, 8), (1, 1), (8, 3), (2, 16)):
-        ctx.set_layout(_layout(wpb, 0, K))
-        assert_parity(results(ctx.filter(b, SS), p.n), want, f"plain E={E} wpb={wpb} K={K}")
-        assert_parity(results(ctx.filter_persistent(b, SS), p.n), want, f"full grid E={E} wpb={wpb} K={K}")
-        ctx.set_layout(_layout(wpb, 2, K))
-        assert_parity(results(ctx.filter_persistent(b, SS), p.n), want, f"queue E={E} wpb={wpb} K={K}")
+    for wpb, K, s0, s1 in ((4, 8, 1, 1), (1, 1, 2, 1), (8, 3, 2, 2), (2, 16, 3, 1), (2, 6, 16, 16)):
+        ctx.set_layout(_layout(wpb, 0, K, s0, s1))
+        tag = f"E={E} wpb={wpb} K={K} spans={s0},{s1}"
+        assert_parity(results(ctx.filter(b, SS), p.n), want, f"plain {tag}")
+        assert_parity(results(ctx.filter_persistent(b, SS), p.n), want, f"full grid {tag}")
+        ctx.set_layout(_layout(wpb, 2, K, s0, s1))
+        assert_parity(results(ctx.filter_persistent(b, SS), p.n), want, f"queue {tag}")
     ctx.check()
 
 
@@ -48,7 +49,7 @@ def test_chunk_uneven_offsets_and_orders(ctx):
     g = torch.Generator().manual_seed(5)
     for offsets in (True, False):
         b = to_device(p, ctx, per_pair=True, offsets=offsets)
-        for lay in (_layout(4, 0, 8), _layout(8, 1, 4), _layout(1, 4, 16)):
+        for lay in (_layout(4, 0, 8), _layout(8, 1, 4, 2, 1), _layout(1, 4, 16, 1, 2)):
             ctx.set_layout(lay)
             assert_parity(results(ctx.filter(b, SS), p.n), want, f"plain {lay}")
             assert_parity(results(ctx.filter_persistent(b, SS), p.n), want, f"persistent {lay}")
@@ -85,7 +86,7 @@ def test_chunk_edge_lengths_and_thresholds(ctx):
                           np.zeros(sel.size, np.uint16))
         wq = {SS: (want[SS][0][sel], want[SS][1][sel])}
         b = to_device(q, ctx, per_pair=True, offsets=True, max_len=512, max_E=me)
-        for lay in (_layout(4, 0, 8), _layout(2, 2, 5)):
+        for lay in (_layout(4, 0, 8), _layout(2, 2, 5, 2, 3)):
             ctx.set_layout(lay)
             assert_parity(results(ctx.filter(b, SS), q.n), wq, f"edges max_E={me} {lay}")
             assert_parity(results(ctx.filter_persistent(b, SS), q.n), wq, f"edges persistent max_E={me} {lay}")

@@ -328,3 +328,55 @@ def test_bucketed_local_range_violation(gpu_ctx):
     mask = np.arange(p.n) != 333
     assert np.array_equal(cnt[mask], want[1][mask].astype(np.int64))
     assert np.array_equal(acc[mask].astype(np.uint8), want[0][mask])
+
+
+def chunk_level_host(y: float) -> int:
+    """Host restatement of the in-chunk level: 16 levels of width 2 over the
+    predicted count clamped to [0, 32] (NaN counts as 0)."""
+    y = np.float32(y)
+    yc = y if y > 0 else np.float32(0)
+    yc = min(yc, np.float32(32))
+    return int(min(15, np.floor(yc * np.float32(0.5))))
+
+
+def test_chunk_level_properties():
+    assert chunk_level_host(float("nan")) == 0 and chunk_level_host(-3.0) == 0
+    assert chunk_level_host(1.999) == 0 and chunk_level_host(2.0) == 1
+    assert chunk_level_host(31.9) == 15 and chunk_level_host(1e9) == 15
+    lv = [chunk_level_host(y) for y in np.linspace(-1, 40, 400)]
+    assert all(a <= b for a, b in zip(lv, lv[1:]))
+
+
+@gpu
+def test_cost_levels_match_predictions(gpu_ctx):
+    """The fused model's level key is 15 - level of its own prediction."""
+    _set_random_model(gpu_ctx, seed=13)
+    for w, n in ((pairgen.UNEVEN_MIX, 30_000), (pairgen.FIXED_250BP, 9_001)):
+        b = _workload_batch(gpu_ctx, w, n)
+        y = gpu_ctx.mlp_predict(b).cpu().numpy()
+        key = gpu_ctx.cost_levels(b).cpu().numpy().astype(np.int64)
+        want = np.array([15 - chunk_level_host(v) for v in y])
+        assert np.array_equal(key, want)
+
+
+@gpu
+def test_filter_keyed_any_key(gpu_ctx):
+    """Any key gives the plain outputs: random, constant, reversed, and the
+    model's own levels."""
+    import paper_1910_03936_amd as paf
+    SS = paf.SNEAKYSNAKE
+    _set_random_model(gpu_ctx, seed=14)
+    for w, n in ((pairgen.UNEVEN_MIX, 12_345), (pairgen.FIXED_250BP, 4_000)):
+        b = _workload_batch(gpu_ctx, w, n)
+        plain = gpu_ctx.filter(b, SS)
+        g = torch.Generator().manual_seed(1)
+        keys = [torch.randint(0, 256, (n,), generator=g, dtype=torch.int32).to(torch.uint8),
+                torch.full((n,), 7, dtype=torch.uint8),
+                (15 - torch.arange(n) % 16).to(torch.uint8),
+                None]
+        for k in keys:
+            key = gpu_ctx.cost_levels(b) if k is None else k.cuda()
+            got = gpu_ctx.filter_keyed(b, key)
+            torch.cuda.synchronize()
+            assert torch.equal(plain[SS][0], got[SS][0]) and torch.equal(plain[SS][1], got[SS][1])
+    gpu_ctx.check()
