@@ -413,39 +413,49 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
     const bool mask_E = GENERAL ? (P.E != nullptr || P.uniform_E < (uint32_t)EMAX)
                                 : (P.uniform_E < (uint32_t)EMAX);
     uint32_t n_ent = n_here;
-    // With a key per pair (the cost model's level), the first window's list
-    // holds the chunk's pairs in ascending key order (a stable counting sort
-    // by wave ballots), so each pass of 64 takes pairs of like cost.
+    // With a key per pair (the cost model's level), the first pass's list
+    // holds the chunk's pairs grouped by the key's top two bits (four cost
+    // classes, a stable counting sort by wave ballots), so each group of 64
+    // takes pairs of like cost.  Finer classes bought less than the sort
+    // cost them.
     const bool keyed = P.order_key != nullptr && plain_out;
     if (keyed) {
-        // Key of pair i of the chunk (16 = no entry: outside the batch or
+        constexpr uint32_t NB = 4, NONE = NB;
+        // Class of pair i of the chunk (NONE = no entry: outside the batch or
         // outside its bounds), with its length and threshold.
         auto key_of = [&](uint32_t i, ChunkEntry& t) -> uint32_t {
             t = ChunkEntry{};
             t.idx = i;
             t.m = P.uniform_len;
             t.E = P.uniform_E;
-            if (i >= n_here) return 16u;
+            if (i >= n_here) return NONE;
             const uint64_t slot = slot0 + i;
             if (GENERAL) {
                 if (P.len) t.m = P.len[slot];
                 if (P.E) t.E = P.E[slot];
-                if (t.m < 1 || t.m > P.max_len || t.E > P.max_E) return 16u;
+                if (t.m < 1 || t.m > P.max_len || t.E > P.max_E) return NONE;
             }
-            return P.order_key[slot] & 15u;
+            return (P.order_key[slot] & 15u) >> 2;
         };
-        uint32_t base[16];
+        // The two pairs of a 128-byte line of sequence words (adjacent
+        // pairs) take the costlier class of the two, so they stay side by
+        // side in the list and their lines are fetched once.
+        auto line_key = [&](uint32_t b) -> uint32_t {
+            const uint32_t o = (uint32_t)__shfl_xor((int)b, 1);
+            return b < NONE && o < b ? o : b;
+        };
+        uint32_t base[NB];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) base[v] = 0;
+        for (uint32_t v = 0; v < NB; ++v) base[v] = 0;
         for (uint32_t g = 0; g < n_here; g += 64) {
             ChunkEntry t;
-            const uint32_t b = key_of(g + (uint32_t)lane, t);
+            const uint32_t b = line_key(key_of(g + (uint32_t)lane, t));
 #pragma unroll
-            for (int v = 0; v < 16; ++v) base[v] += (uint32_t)__builtin_popcountll(__ballot(b == (uint32_t)v));
+            for (uint32_t v = 0; v < NB; ++v) base[v] += (uint32_t)__builtin_popcountll(__ballot(b == v));
         }
         uint32_t run = 0;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
+        for (uint32_t v = 0; v < NB; ++v) {
             const uint32_t c = base[v];
             base[v] = run;
             run += c;
@@ -454,10 +464,10 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
         for (uint32_t g = 0; g < n_here; g += 64) {
             const uint32_t i = g + (uint32_t)lane;
             ChunkEntry t;
-            const uint32_t b = key_of(i, t);
+            const uint32_t b = line_key(key_of(i, t));
             if (i < n_here) {
                 const uint64_t slot = slot0 + i;
-                if (b == 16u) {
+                if (b == NONE) {
                     atomicOr(P.err, 1u);
                     P.cnt[0][slot] = 0;
                 } else if (GENERAL) {
@@ -466,14 +476,14 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
             }
             uint32_t pos = 0;
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const uint64_t mv = __ballot(b == (uint32_t)v);
+            for (uint32_t v = 0; v < NB; ++v) {
+                const uint64_t mv = __ballot(b == v);
                 const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mv >> 32),
                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)mv, 0u));
-                if (b == (uint32_t)v) pos = base[v] + below;
+                if (b == v) pos = base[v] + below;
                 base[v] += (uint32_t)__builtin_popcountll(mv);
             }
-            if (b < 16u) L.ent[pos] = chunk_pack(t);
+            if (b < NONE) L.ent[pos] = chunk_pack(t);
         }
     }
     // Each pass walks windows [w, w + span) with the same lanes; the pairs

@@ -115,33 +115,42 @@ __device__ __forceinline__ void count_long(const WindowWords& q, uint32_t* z) {
 
 // Fraction features of the diagonals inside the pair's own threshold; those
 // beyond it are 0.  `masked` is false when every lane of the wave has E >= EF.
-template <int EF>
+// Slot of diagonal index i (d = i - EF) in the feature vector: 32 + d in the
+// 64-slot layout, 2 + i in the compact one (m/512, E/32, then the 2 EF + 1
+// diagonals; the model's other inputs are zero and contribute nothing).
+template <int EF, bool CK>
+__device__ __forceinline__ constexpr int diag_slot(int i) {
+    return CK ? 2 + i : 32 + i - EF;
+}
+
+template <int EF, bool CK>
 __device__ __forceinline__ void store_fractions(const float* v, uint32_t E, bool masked, float* f) {
     constexpr int D = 2 * EF + 1;
     if (EF <= 15 && !masked) {
 #pragma unroll
-        for (int i = 0; i < D; ++i) f[32 + i - EF] = v[i];
+        for (int i = 0; i < D; ++i) f[diag_slot<EF, CK>(i)] = v[i];
     } else {
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             const int d = i - EF;
             const uint32_t ad = (uint32_t)(d < 0 ? -d : d);
-            f[32 + d] = ad <= E ? v[i] : 0.0f;
+            f[diag_slot<EF, CK>(i)] = ad <= E ? v[i] : 0.0f;
         }
     }
 }
 
-template <int EF>
+template <int EF, bool CK = false>
 __device__ __forceinline__ void pair_features(const uint64_t* rd, const uint64_t* rf, uint32_t m,
                                               uint32_t E, float* f, bool all_long, bool masked) {
     constexpr int D = 2 * EF + 1;
+    constexpr int NF = CK ? 32 : 64;
     uint32_t z[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) z[i] = 0;
     const int W = (int)((m + 31) >> 5);
     float v[D];
 #pragma unroll
-    for (int i = 0; i < 64; ++i) f[i] = 0.0f;
+    for (int i = 0; i < NF; ++i) f[i] = 0.0f;
     f[0] = (float)m * (1.0f / 512.0f);
     f[1] = (float)E * (1.0f / 32.0f);
     // The fast path doubles the feature code; above 15 diagonals per side it
@@ -167,7 +176,68 @@ __device__ __forceinline__ void pair_features(const uint64_t* rd, const uint64_t
 #pragma unroll
         for (int i = 0; i < D; ++i) v[i] = (float)z[i] * rcp;
     }
-    store_fractions<EF>(v, E, masked, f);
+    store_fractions<EF, CK>(v, E, masked, f);
+}
+
+// Fast path of the compact layout (every read of the wave at least 64 + EF
+// long, every lane's E >= EF): blocked-cell counts of the first two windows
+// straight from the packed words, converted to the bf16 inputs and stored
+// as the pair's staged row.
+__device__ __forceinline__ uint32_t or_xor3_m(uint32_t a, uint32_t t, uint32_t b) {
+    return __builtin_amdgcn_bitop3_b32(a, t, b, 0xDE);   // t | (a ^ b)
+}
+
+template <int EF, int K, int I = 0>
+__device__ __forceinline__ void blocked_counts(uint32_t plo, uint32_t phi, uint32_t clo, uint32_t chi,
+                                               uint32_t nlo, uint32_t nhi, uint32_t flo, uint32_t fhi,
+                                               uint32_t* z) {
+    if constexpr (I < 2 * EF + 1) {
+        constexpr int d = I - EF;
+        uint32_t lo, hi;
+        if constexpr (d > 0) {
+            lo = funnel(nlo, clo, d);
+            hi = funnel(nhi, chi, d);
+        } else if constexpr (d == 0) {
+            lo = clo;
+            hi = chi;
+        } else {
+            lo = funnel(clo, plo, 32 + d);
+            hi = funnel(chi, phi, 32 + d);
+        }
+        uint32_t t = lo ^ flo;
+        if constexpr (K == 0) t |= left_vacant<d>();
+        z[I] += __builtin_popcount(or_xor3_m(hi, t, fhi));
+        blocked_counts<EF, K, I + 1>(plo, phi, clo, chi, nlo, nhi, flo, fhi, z);
+    }
+}
+
+template <int EF>
+__device__ __forceinline__ void stage_compact_fast(uint64_t r0, uint64_t r1, uint64_t r2, uint64_t f0,
+                                                   uint64_t f1, uint32_t m, uint32_t E, uint16_t* row) {
+    constexpr int D = 2 * EF + 1;
+    uint32_t z[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) z[i] = 0;
+    const uint32_t r0l = (uint32_t)r0, r0h = (uint32_t)(r0 >> 32), r1l = (uint32_t)r1,
+                   r1h = (uint32_t)(r1 >> 32), r2l = (uint32_t)r2, r2h = (uint32_t)(r2 >> 32);
+    blocked_counts<EF, 0>(0u, 0u, r0l, r0h, r1l, r1h, (uint32_t)f0, (uint32_t)(f0 >> 32), z);
+    blocked_counts<EF, 1>(r0l, r0h, r1l, r1h, r2l, r2h, (uint32_t)f1, (uint32_t)(f1 >> 32), z);
+    float v[32];
+    v[0] = (float)m * (1.0f / 512.0f);
+    v[1] = (float)E * (1.0f / 32.0f);
+#pragma unroll
+    for (int i = 0; i < D; ++i) v[2 + i] = __builtin_fmaf((float)z[i], -1.0f / 64.0f, 1.0f);
+#pragma unroll
+    for (int i = D + 2; i < 32; ++i) v[i] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        uint4 u;
+        u.x = bf16_bits(v[8 * c + 0]) | ((uint32_t)bf16_bits(v[8 * c + 1]) << 16);
+        u.y = bf16_bits(v[8 * c + 2]) | ((uint32_t)bf16_bits(v[8 * c + 3]) << 16);
+        u.z = bf16_bits(v[8 * c + 4]) | ((uint32_t)bf16_bits(v[8 * c + 5]) << 16);
+        u.w = bf16_bits(v[8 * c + 6]) | ((uint32_t)bf16_bits(v[8 * c + 7]) << 16);
+        *reinterpret_cast<uint4*>(&row[8 * c]) = u;
+    }
 }
 
 struct PairRef {
@@ -257,6 +327,7 @@ __host__ __device__ __forceinline__ uint32_t chunk_level(float y) {
 struct KeyParams {
     FilterParams P;
     const uint16_t* w1f;
+    const uint16_t* w1b;   // row-major bf16 W1 [128][64] (compact-feature gather)
     const uint16_t* w2f;
     const float* master;
     const float* w3r;
@@ -290,25 +361,43 @@ __device__ __forceinline__ FeatWords feat_words(const FilterParams& P, uint64_t 
     return q;
 }
 
-template <int EF>
+template <int EF, bool CK>
 __device__ __forceinline__ void features_from_words(const FeatWords& w, float* f, bool all_long,
                                                     bool masked) {
     uint64_t rd[3] = {w.r0, w.r1, w.r2};
     uint64_t rf[2] = {w.f0, w.f1};
-    pair_features<EF>(rd, rf, w.m, w.E, f, all_long, masked);
+    pair_features<EF, CK>(rd, rf, w.m, w.E, f, all_long, masked);
 }
 
+// With at most 14 diagonals per side the non-zero inputs (m/512, E/32 and
+// the 2 EF + 1 fractions) fit one 32-wide k-tile: the kernel stages that
+// compact vector and layer 1 takes one matrix product per tile instead of
+// two (the other 32 inputs are zero and add nothing).
 template <int EF>
 __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
-    __shared__ __attribute__((aligned(16))) uint16_t sW1[8 * 2 * 64 * 8];
+    constexpr bool CK = 2 * EF + 3 <= 32;
+    constexpr int KT1 = CK ? 1 : 2;          // layer-1 k-tiles
+    constexpr int NF = 32 * KT1;             // staged inputs per pair
+    __shared__ __attribute__((aligned(16))) uint16_t sW1[8 * KT1 * 64 * 8];
     __shared__ __attribute__((aligned(16))) uint16_t sW2[8 * 4 * 64 * 8];
     __shared__ __attribute__((aligned(16))) float sB1[kHid];
     __shared__ __attribute__((aligned(16))) float sB2[kHid];
     __shared__ float sW3[kHid];
-    __shared__ __attribute__((aligned(16))) uint16_t sX[kKeyWaves][64][72];
+    __shared__ __attribute__((aligned(16))) uint16_t sX[kKeyWaves][64][NF + 8];
     const FilterParams& P = K.P;
-    for (int i = threadIdx.x; i < 8 * 2 * 64; i += blockDim.x)
-        reinterpret_cast<uint4*>(sW1)[i] = reinterpret_cast<const uint4*>(K.w1f)[i];
+    if constexpr (CK) {
+        // Fragment order for one k-tile: lane (q, g) of m-tile mt holds
+        // W1[16 mt + q][input of compact slot 8 g + j], j = 0..7.
+        for (int i = threadIdx.x; i < 8 * 64 * 8; i += blockDim.x) {
+            const int j = i & 7, ln = (i >> 3) & 63, mt = i >> 9;
+            const int h = 16 * mt + (ln & 15), slot = 8 * (ln >> 4) + j;
+            const int in = slot < 2 ? slot : (slot - 2 <= 2 * EF ? 32 - EF + (slot - 2) : -1);
+            sW1[i] = in < 0 ? (uint16_t)0 : K.w1b[h * kFeat + in];
+        }
+    } else {
+        for (int i = threadIdx.x; i < 8 * 2 * 64; i += blockDim.x)
+            reinterpret_cast<uint4*>(sW1)[i] = reinterpret_cast<const uint4*>(K.w1f)[i];
+    }
     for (int i = threadIdx.x; i < 8 * 4 * 64; i += blockDim.x)
         reinterpret_cast<uint4*>(sW2)[i] = reinterpret_cast<const uint4*>(K.w2f)[i];
     for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
@@ -325,18 +414,25 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
     FeatWords cur = feat_words(P, (uint64_t)tile * 64 + lane);
     for (; tile < P.n_tiles; tile += stride) {
         const uint64_t p = (uint64_t)tile * 64 + lane;
-        {
-            float f[64];
-            const bool all_long = !wave_any(cur.valid && cur.m < 64u + EF);
-            const bool masked = wave_any(cur.valid && cur.E < (uint32_t)EF);
+        const bool all_long = !wave_any(cur.valid && cur.m < 64u + EF);
+        const bool masked = wave_any(cur.valid && cur.E < (uint32_t)EF);
+        if (CK && all_long && !masked) {
             if (cur.valid) {
-                features_from_words<EF>(cur, f, all_long, masked);
+                stage_compact_fast<EF>(cur.r0, cur.r1, cur.r2, cur.f0, cur.f1, cur.m, cur.E, &sX[wave][lane][0]);
             } else {
 #pragma unroll
-                for (int i = 0; i < 64; ++i) f[i] = 0.0f;
+                for (int c = 0; c < NF / 8; ++c) *reinterpret_cast<uint4*>(&sX[wave][lane][8 * c]) = uint4{0, 0, 0, 0};
+            }
+        } else {
+            float f[NF];
+            if (cur.valid) {
+                features_from_words<EF, CK>(cur, f, all_long, masked);
+            } else {
+#pragma unroll
+                for (int i = 0; i < NF; ++i) f[i] = 0.0f;
             }
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
+            for (int c = 0; c < NF / 8; ++c) {
                 uint4 v;
                 v.x = bf16_bits(f[8 * c + 0]) | ((uint32_t)bf16_bits(f[8 * c + 1]) << 16);
                 v.y = bf16_bits(f[8 * c + 2]) | ((uint32_t)bf16_bits(f[8 * c + 3]) << 16);
@@ -352,9 +448,9 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
         wave_lds_sync();
         // Layer-1 operand B: X^T, lane (pair 16 nt + q16, group grp) holds
         // features 32 kt + 8 grp .. +7 of its pair.
-        bf16x8 xf[2][4];
+        bf16x8 xf[KT1][4];
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt)
+        for (int kt = 0; kt < KT1; ++kt)
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
                 xf[kt][nt] = *reinterpret_cast<const bf16x8*>(&sX[wave][16 * nt + q16][32 * kt + 8 * grp]);
@@ -368,11 +464,14 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
                 const int mt1 = 2 * kt2 + half;
                 const f32x4 bias1 = *reinterpret_cast<const f32x4*>(&sB1[16 * mt1 + 4 * grp]);
                 f32x4 acc1[4];
+                const bf16x8 a1a = *reinterpret_cast<const bf16x8*>(&sW1[((mt1 * KT1 + 0) * 64 + lane) * 8]);
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt) acc1[nt] = mfma(a1_at(sW1, mt1, 0, lane), xf[0][nt], bias1);
-                const bf16x8 a1b = a1_at(sW1, mt1, 1, lane);
+                for (int nt = 0; nt < 4; ++nt) acc1[nt] = mfma(a1a, xf[0][nt], bias1);
+                if constexpr (KT1 == 2) {
+                    const bf16x8 a1b = *reinterpret_cast<const bf16x8*>(&sW1[((mt1 * KT1 + 1) * 64 + lane) * 8]);
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt) acc1[nt] = mfma(a1b, xf[1][nt], acc1[nt]);
+                    for (int nt = 0; nt < 4; ++nt) acc1[nt] = mfma(a1b, xf[KT1 - 1][nt], acc1[nt]);
+                }
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
@@ -804,6 +903,7 @@ hipError_t launch_learned_buckets(const MlpDev& m, const FilterParams& p, int nu
     KeyParams kp;
     kp.P = p;
     kp.w1f = m.w1f;
+    kp.w1b = m.w1b;
     kp.w2f = m.w2f;
     kp.master = m.master;
     kp.w3r = m.w3r;

@@ -149,12 +149,23 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-30))
 
 
+_SHORT_MIX = pairgen.Workload("short reads around the 64 + E edge", 10_000, (20, 64, 70, 75), 12, 0.5,
+                              fixed_E=6, seed=pairgen.SEED_BASE + 40)
+
+
 @gpu
-def test_forward_and_fused_predict_match_oracle(gpu_ctx):
+@pytest.mark.parametrize("wname", ["uneven", "fixed250", "fixed250_E14", "fixed250_E0", "short"])
+def test_forward_and_fused_predict_match_oracle(gpu_ctx, wname):
+    """The fused kernel (64-input layout for more than 14 diagonals per side,
+    compact 32-input layout otherwise, fast and general feature paths)
+    against the oracle's forward on the 64 features."""
+    wl = {"uneven": pairgen.UNEVEN_MIX, "fixed250": pairgen.FIXED_250BP,
+          "fixed250_E14": pairgen.FIXED_250BP.with_E(14), "fixed250_E0": pairgen.FIXED_250BP.with_E(0),
+          "short": _SHORT_MIX}[wname]
     p = _set_random_model(gpu_ctx)
     w = om.working_weights(p)
     n = 5000
-    b = _workload_batch(gpu_ctx, pairgen.UNEVEN_MIX, n)
+    b = _workload_batch(gpu_ctx, wl, n)
     feats = gpu_ctx.features(b)
     y_gemm = gpu_ctx.mlp_forward(feats).cpu().numpy()
     y_fused = gpu_ctx.mlp_predict(b).cpu().numpy()
