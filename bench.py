@@ -146,11 +146,13 @@ def main():
     ap.add_argument("--train-pairs", type=int, default=2_000_000)
     ap.add_argument("--no-learned", action="store_true", help="time the plain filter only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="fixed250", choices=["fixed250", "uneven", "learned-uneven", "stream"],
-                    help="fixed250 (default): 10M x 250 bp at E (plain and learned-bucketed); uneven: 50M "
-                         "pairs of mixed lengths in the persistent launch, default vs autotuned layout; "
-                         "learned-uneven: the same batch, learned-bucketed vs plain; stream: 200M pairs "
-                         "streamed from pinned host memory in 8M-pair chunks")
+    ap.add_argument("--workload", default="fixed250",
+                    choices=["fixed250", "filters", "uneven", "learned-uneven", "stream"],
+                    help="fixed250 (default): 10M x 250 bp at E (plain and learned-bucketed); filters: the "
+                         "same pairs at E = 0, 5, 10, 25 with SneakySnake, GateKeeper, Shouji and all three "
+                         "on one map; uneven: 50M pairs of mixed lengths in the persistent launch, default "
+                         "vs autotuned layout; learned-uneven: the same batch, learned-bucketed vs plain; "
+                         "stream: 200M pairs streamed from pinned host memory in 8M-pair chunks")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain copy kernel of known size (counter calibration)")
     args = ap.parse_args()
@@ -160,9 +162,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}): this build has no "
-              f"multi-GPU path; pairs are independent, so a multi-GPU run would shard the batch "
-              f"(see DESIGN.md).", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}): there is no "
+              f"multi-GPU path; pairs are independent, so several GPUs would each filter a contiguous "
+              f"range of the batch with no exchange.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -171,6 +173,9 @@ def main():
     import paper_1910_03936_amd as paf
     from paper_1910_03936_amd import costmodel
 
+    if args.workload == "filters":
+        filters_workload(args)
+        return
     if args.workload != "fixed250":
         other_workload(args)
         return
@@ -310,6 +315,52 @@ def emit(args, metric_value, ms, workload_desc, cfg, roofline, cpu, extra):
            "roofline": roofline, "cpu_baseline": cpu}
     rec.update(extra)
     print(json.dumps(rec), flush=True)
+
+
+def filters_workload(args):
+    """10M x 250 bp pairs at E = 0, 5, 10, 25: each decision stage alone and all
+    three on the same map (one plain launch each)."""
+    import dataclasses
+
+    import torch
+
+    import pairgen
+    import paper_1910_03936_amd as paf
+
+    ctx = paf.Context(0)
+    dev = torch.device("cuda", 0)
+    w = pairgen.FIXED_250BP
+    n = args.pairs or w.n_pairs
+    base, _ = build_batch(ctx, w, n, dev)
+    W = paf.words_for(250)
+    SS, GK, SH = paf.SNEAKYSNAKE, paf.GATEKEEPER, paf.SHOUJI
+    sets = {"sneakysnake": SS, "gatekeeper": GK, "shouji": SH, "all three": SS | GK | SH}
+    by_E, steps = {}, max(3, args.steps // 2)
+    for E in (0, 5, 10, 25):
+        b = dataclasses.replace(base, uniform_E=E, max_E=E)
+        row = {}
+        for name, f in sets.items():
+            out = ctx.alloc_out(n, f, dev)
+            per, tot, _ = time_steps(lambda: ctx.filter(b, f, out=out), steps, args.warmup)
+            ctx.check()
+            ms = sum(per) / len(per)
+            nf = bin(f).count("1")
+            gbs = n * (2 * W * 8 + nf * (2 + 1 / 8)) / (ms / 1e3) / 1e9
+            row[name] = {"ms": round(ms, 4), "pairs_per_s": n / (ms / 1e3), "hbm_GBps": round(gbs, 1)}
+            del out
+        by_E[str(E)] = row
+        log(f"E={E}: " + ", ".join(f"{k} {v['ms']:.3f} ms" for k, v in row.items()))
+    r10 = by_E["10"]["all three"]
+    gbs = r10["hbm_GBps"]
+    emit(args, r10["pairs_per_s"], r10["ms"],
+         f"{n} pairs, 250 bp, 2-bit packed, 70% unrelated, k~U{{0..40}}; SneakySnake, GateKeeper and Shouji on "
+         f"one map, plain launch; value at E=10",
+         {"pairs": n, "read_len": 250, "E": [0, 5, 10, 25], "filters": "each alone and all three"},
+         {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+          "traffic": None, "kernel": "filter_kernel<Whole, E=10, plain> (all three stages)",
+          "kernel_ms": r10["ms"], "alg_bytes_per_pair": round(2 * W * 8 + 3 * (2 + 1 / 8), 3)},
+         None, {"by_E": by_E})
+    ctx.close()
 
 
 def other_workload(args):
