@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpaf.so")
-SOURCES = ["filter.hip", "mlp.hip", "api.hip", "stream.hip"]
+SOURCES = ["filter.hip", "whole.hip", "mlp.hip", "api.hip", "stream.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -27,7 +27,7 @@ def _hipcc() -> str:
     return os.path.join(root, "bin", "hipcc")
 
 
-def build(verbose: bool = False, jobs: int = 3) -> str:
+def build(verbose: bool = False, jobs: int = 5) -> str:
     """Compile every source to an object in _build/, then link libpaf.so."""
     out_dir = os.path.join(HERE, "_build")
     os.makedirs(out_dir, exist_ok=True)

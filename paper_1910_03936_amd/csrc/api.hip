@@ -174,7 +174,7 @@ paf_status run_persistent(paf_ctx* ctx, FilterParams p, Engine eng, int emax, co
     // SneakySnake alone with a chunk size: the compacting engine; its queue
     // and grid count chunks instead of tiles.
     if (eng == Engine::Snake && L.chunk_tiles > 0) eng = Engine::Chunk;
-    const void* k = filter_kernel_ptr(eng, general, emax);
+    const void* k = filter_kernel_ptr(eng, general, emax, p.filters);
     if (!k) return fail(PAF_ERR_RANGE, "no kernel for this threshold");
     if (L.waves_per_block > max_waves(eng)) return fail(PAF_ERR_ARG, "too many waves per block for this engine");
     LaunchShape sh;
@@ -422,7 +422,7 @@ paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, co
     }
     sh.blocks = (uint32_t)((units + sh.waves_per_block - 1) / sh.waves_per_block);
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    PAF_HIP(allow_lds(filter_kernel_ptr(eng, general, emax), sh.lds_bytes), "hipFuncSetAttribute");
+    PAF_HIP(allow_lds(filter_kernel_ptr(eng, general, emax, p.filters), sh.lds_bytes), "hipFuncSetAttribute");
     PAF_HIP(launch_filter(p, eng, general, emax, sh, (hipStream_t)stream), "filter launch");
     return PAF_OK;
 }

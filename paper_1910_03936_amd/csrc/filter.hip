@@ -1,220 +1,24 @@
-// Pre-alignment filter kernels for gfx950.
+// Pre-alignment filter kernels for gfx950: SneakySnake engines, encoder and
+// small helpers.  (GateKeeper and Shouji, which read the whole map, are in
+// whole.hip.)
 //
-// One lane per (read, reference segment) pair; a wave holds a tile of 64
-// pairs.  Sequences arrive 2-bit packed (planar inside each uint64 word, see
-// paf.h) and are staged per wave in LDS, word-major ([word][lane]) so that a
-// lane reads its own words without bank conflicts.  The neighbourhood map
+// One lane per (read, reference segment) pair.  Sequences arrive 2-bit
+// packed (planar inside each uint64 word, see paf.h).  The neighbourhood map
 // (Eq. 6.1; the unweighted maze of Eq. 8.2) is never materialised in HBM: for
-// one 32-column window at a time each lane builds the 2E+1 diagonal mismatch
-// words in VGPRs with funnel shifts (v_alignbit) and 3-input logic
-// (v_bitop3).  Diagonal d compares ref[c] with read[c + d].
+// one 32-column window at a time each lane builds the 2E+1 diagonal words in
+// VGPRs with funnel shifts (v_alignbit) and 3-input logic (v_bitop3).
+// Diagonal d compares ref[c] with read[c + d].
 //
-// Two engines share the map build:
-//  * Snake: SneakySnake only (Ch. 8, Sec. 8.4).  Windows are built lazily and
-//    a lane stops as soon as its decision is known, so most rejected pairs
-//    touch one or two windows.  A probe of all diagonals at column c is
-//    max_d ffbl(M_d >> s): the position of the first obstacle of the deepest
-//    pipe, found with one shift, one find-first-bit and a third of a max3 per
-//    diagonal.
-//  * Whole: GateKeeper (Ch. 5) and/or Shouji (Ch. 6), which read the whole map,
-//    plus SneakySnake on the same map when asked for.
-//
-// The window index is wave-uniform: every lane still working is in the same
-// window, so the map words live in registers with compile-time indices.
-#include "paf_internal.h"
-#include "paf_map.h"
+// Two SneakySnake engines (Ch. 8, Sec. 8.4):
+//  * per tile: a wave holds 64 pairs staged in LDS, word-major ([word][lane]),
+//    and walks the windows in step until all 64 are decided;
+//  * compacting: a wave owns a chunk of tiles and regroups the pairs still
+//    undecided into full waves between passes (see chunk_snake).
+#include "paf_tile.h"
 
 namespace paf {
 
 namespace {
-
-template <int EMAX>
-struct DeadMask {
-    using T = typename std::conditional<(2 * EMAX + 1 <= 32), uint32_t, uint64_t>::type;
-};
-
-// Per-lane view of one pair of the tile.
-struct PairSlot {
-    uint64_t slot;   // position in the launch order
-    uint64_t id;     // original pair index
-    bool valid;      // in range and passed the device-side checks
-    bool in_batch;   // slot < n_pairs
-    uint32_t m, E;
-    uint32_t W;      // words per sequence
-};
-
-template <bool GENERAL>
-__device__ __forceinline__ PairSlot load_slot(const FilterParams& P, uint64_t tile, int lane,
-                                              uint64_t& off) {
-    PairSlot s;
-    s.slot = tile * 64 + (uint64_t)lane;
-    s.in_batch = s.slot < P.n_pairs;
-    s.valid = s.in_batch;
-    s.id = s.slot;
-    s.m = P.uniform_len;
-    s.E = P.uniform_E;
-    off = 0;
-    if (GENERAL) {
-        if (s.valid && P.perm) s.id = P.perm[s.slot];
-        if (s.valid) {
-            if (P.len) s.m = P.len[s.id];
-            if (P.E) s.E = P.E[s.id];
-            off = P.word_offset ? P.word_offset[s.id] : s.id * (uint64_t)P.stride_words;
-            if (s.m < 1 || s.m > P.max_len || s.E > P.max_E) {
-                atomicOr(P.err, 1u);
-                s.valid = false;
-            }
-        }
-    } else {
-        off = s.id * (uint64_t)P.stride_words;
-    }
-    if (!s.valid) s.m = 0;
-    s.W = (s.m + 31) >> 5;
-    return s;
-}
-
-// Stage the tile's words into the wave's LDS rows.
-template <bool GENERAL>
-__device__ __forceinline__ void stage_tile(const FilterParams& P, uint64_t tile, int lane,
-                                           const PairSlot& s, uint64_t off, uint64_t* rdL,
-                                           uint64_t* rfL) {
-    const uint32_t WM = P.wmax;
-    if (!GENERAL) {
-        // The tile's pairs are contiguous: pair-major rows of stride_words
-        // words.  Coalesced 8-byte loads over the whole tile region, then a
-        // transposed write into [word][lane].
-        const uint32_t S = P.stride_words;
-        const uint64_t base = tile * 64 * (uint64_t)S;
-        const uint64_t limit = P.n_pairs * (uint64_t)S;
-        const uint32_t total = 64u * S;
-        uint32_t q = (uint32_t)lane;
-        uint32_t pr = q / S, k = q - pr * S;
-        const uint32_t dp = 64u / S, dk = 64u - dp * S;
-        for (; q < total; q += 64) {
-            if (k < WM) {
-                const uint64_t g = base + q;
-                const bool ok = g < limit;
-                rdL[k * kLdsRow + pr] = ok ? P.reads[g] : 0ull;
-                rfL[k * kLdsRow + pr] = ok ? P.refs[g] : 0ull;
-            }
-            pr += dp;
-            k += dk;
-            if (k >= S) { k -= S; pr += 1; }
-        }
-        // Words past a pair's length are zero already (the packer zeroes the
-        // tail of the last word and the layout has no words beyond W).
-    } else {
-        // Pairs sit anywhere (offsets, bucketed order): groups of WM adjacent
-        // lanes read one pair's row of words together, so every load
-        // instruction covers whole rows; the row's offset and length come
-        // from the lane that owns the pair.
-        const uint32_t offlo = (uint32_t)off, offhi = (uint32_t)(off >> 32);
-        const uint32_t wv = s.valid ? s.W : 0u;
-        uint32_t pr = (uint32_t)lane / WM, k = (uint32_t)lane - pr * WM;
-        const uint32_t dp = 64u / WM, dk = 64u - dp * WM;
-        for (uint32_t r = 0; r < WM; ++r) {
-            const uint64_t o = ((uint64_t)__shfl(offhi, (int)pr) << 32) | __shfl(offlo, (int)pr);
-            const bool ok = k < (uint32_t)__shfl(wv, (int)pr);
-            rdL[k * kLdsRow + pr] = ok ? P.reads[o + k] : 0ull;
-            rfL[k * kLdsRow + pr] = ok ? P.refs[o + k] : 0ull;
-            pr += dp;
-            k += dk;
-            if (k >= WM) { k -= WM; pr += 1; }
-        }
-    }
-    wave_lds_sync();
-}
-
-template <int EMAX, int I = 0>
-__device__ __forceinline__ void build_snake_map(const WindowWords& q, bool boundary, uint32_t* M) {
-    if constexpr (I < 2 * EMAX + 1) {
-        constexpr int d = I - EMAX;
-        uint32_t x = diag_raw<d>(q);
-        if (boundary) x |= diag_vacant<d>(q);
-        M[I] = x;
-        build_snake_map<EMAX, I + 1>(q, boundary, M);
-    }
-}
-
-// Whole-map engine: blocked map for SneakySnake/Shouji (vacant and past-end
-// cells are 1) and GateKeeper's map (vacant and past-end cells are 0).
-template <int d>
-__device__ __forceinline__ void diag_both(const WindowWords& q, uint32_t& Mh, uint32_t& G) {
-    const uint32_t x = diag_raw<d>(q);
-    const uint32_t v = diag_vacant<d>(q);
-    Mh = x | v | q.vc;          // q.vc doubles as "column >= m" for this window
-    G = x & ~v & ~q.vc;
-}
-
-// ---------------------------------------------------------------------------
-// SneakySnake: state of one lane's snake.
-struct Snake {
-    uint32_t c, e;
-    bool act, acc;
-    uint32_t cnt;
-};
-
-__device__ __forceinline__ void snake_finish(Snake& z, bool accept, uint32_t count) {
-    z.act = false;
-    z.acc = accept;
-    z.cnt = count;
-}
-
-// Probe every diagonal from column c (window-relative shift s) and move the
-// snake: follow the deepest pipe, then cross its obstacle (one edit, one
-// column), or finish.  `x` holds the map words of the window; `dead` marks,
-// for a lane that enters the window still inside a pipe, the diagonals whose
-// pipes ended before the window (bit i = diagonal i); it applies only to the
-// window's first column.
-template <int EMAX, typename DT>
-__device__ __forceinline__ void snake_window(Snake& z, const uint32_t* M, uint32_t w, uint32_t m,
-                                             uint32_t E, bool& cont, DT& dead) {
-    constexpr int D = 2 * EMAX + 1;
-    const uint32_t wend = 32u * (w + 1);
-    while (z.act && z.c < wend) {
-        const uint32_t s = z.c - 32u * w;
-        uint32_t best = 0;
-        if (cont) {
-            // s == 0 here.
-#pragma unroll
-            for (int i = 0; i < D; ++i) best = max(best, ffbl(M[i] | (uint32_t)((dead >> i) & 1u)));
-        } else {
-#pragma unroll
-            for (int i = 0; i < D; ++i) best = max(best, ffbl(M[i] >> s));
-        }
-        if (best == 0xFFFFFFFFu) {
-            // Some pipe runs past the window's end.
-            if (wend >= m) {
-                snake_finish(z, true, z.e);
-            } else {
-                DT dm = 0;
-                if (cont) {
-#pragma unroll
-                    for (int i = 0; i < D; ++i)
-                        dm |= (DT)(((M[i] | (uint32_t)((dead >> i) & 1u)) != 0u) ? 1u : 0u) << i;
-                } else {
-#pragma unroll
-                    for (int i = 0; i < D; ++i) dm |= (DT)(((M[i] >> s) != 0u) ? 1u : 0u) << i;
-                }
-                dead = dm;
-                cont = true;
-                z.c = wend;
-                return;
-            }
-        } else {
-            cont = false;
-            const uint32_t R = z.c + best;     // column of the obstacle
-            if (R >= m) {
-                snake_finish(z, true, z.e);
-            } else {
-                z.e += 1;
-                z.c = R + 1;
-                if (z.e > E) snake_finish(z, false, E + 1);
-                else if (z.c >= m) snake_finish(z, true, z.e);
-            }
-        }
-    }
-}
 
 template <int EMAX, bool GENERAL>
 __device__ void snake_tile(const FilterParams& P, uint64_t tile, int lane, uint64_t* rdL,
@@ -707,230 +511,21 @@ size_t chunk_bytes_for(int emax, uint32_t K) {
     return emax <= 15 ? chunk_wave_bytes_t<15, GENERAL>(K) : chunk_wave_bytes_t<31, GENERAL>(K);
 }
 
-// ---------------------------------------------------------------------------
-// Whole-map engine.
-
-// GateKeeper's amendment of one window word (Ch. 5, Sec. 5.2.2; SRS of
-// Sec. 3.2.1): a zero inside a streak of one or two zeros bounded by ones on
-// both sides becomes one.  L1/L2 are the bits one/two columns to the left,
-// R1/R2 to the right (taken from the neighbouring windows).
-__device__ __forceinline__ uint32_t amend_word(uint32_t g, uint32_t prev, uint32_t next) {
-    const uint32_t L1 = funnel(g, prev, 31);
-    const uint32_t L2 = funnel(g, prev, 30);
-    const uint32_t R1 = funnel(next, g, 1);
-    const uint32_t R2 = funnel(next, g, 2);
-    return g | (L1 & (R1 | R2)) | (R1 & (L1 | L2));
-}
-
-// Shouji: bit-sliced best 4-column segment per window start column.
-struct ShoujiBest {
-    uint32_t o0, o1, o2;      // ones in the best segment (bit-sliced, 0..4)
-    uint32_t b0, b1, b2, b3;  // the best segment's bits
-};
-
-__device__ __forceinline__ void shouji_candidate(ShoujiBest& bs, uint32_t cur, uint32_t nxt,
-                                                 bool first) {
-    const uint32_t B0 = cur;
-    const uint32_t B1 = funnel(nxt, cur, 1);
-    const uint32_t B2 = funnel(nxt, cur, 2);
-    const uint32_t B3 = funnel(nxt, cur, 3);
-    const uint32_t s01 = B0 ^ B1, c01 = B0 & B1, s23 = B2 ^ B3, c23 = B2 & B3;
-    const uint32_t o0 = s01 ^ s23;
-    const uint32_t cm = s01 & s23;
-    const uint32_t o1 = c01 ^ c23 ^ cm;
-    const uint32_t o2 = c01 & c23;
-    if (first) {
-        bs = {o0, o1, o2, B0, B1, B2, B3};
-        return;
-    }
-    // Fewer ones wins; on a tie, a segment that starts with a zero beats one
-    // that does not; otherwise the earlier diagonal is kept.
-    const uint32_t t0 = ~o0 & bs.o0;
-    const uint32_t e1 = ~(o1 ^ bs.o1);
-    const uint32_t t1 = (~o1 & bs.o1) | (e1 & t0);
-    const uint32_t e2 = ~(o2 ^ bs.o2);
-    const uint32_t lt = (~o2 & bs.o2) | (e2 & t1);
-    const uint32_t eq = e2 & e1 & ~(o0 ^ bs.o0);
-    const uint32_t rep = lt | (eq & ~B0 & bs.b0);
-    bs.o0 = (rep & o0) | (~rep & bs.o0);
-    bs.o1 = (rep & o1) | (~rep & bs.o1);
-    bs.o2 = (rep & o2) | (~rep & bs.o2);
-    bs.b0 = (rep & B0) | (~rep & bs.b0);
-    bs.b1 = (rep & B1) | (~rep & bs.b1);
-    bs.b2 = (rep & B2) | (~rep & bs.b2);
-    bs.b3 = (rep & B3) | (~rep & bs.b3);
-}
-
-// Sequential store into the Shouji bit-vector for the 32 windows starting in
-// this window (Sec. 6.2.2): the best segment overwrites the vector's four
-// bits when it holds strictly more zeros.  S covers columns [32w, 32w+64).
-template <int J = 0>
-__device__ __forceinline__ void shouji_store(const ShoujiBest& bs, uint32_t& S_lo, uint32_t& S_hi,
-                                             uint32_t ncols) {
-    if constexpr (J < 32) {
-        const uint32_t V = ((bs.b0 >> J) & 1u) | (((bs.b1 >> J) & 1u) << 1) |
-                           (((bs.b2 >> J) & 1u) << 2) | (((bs.b3 >> J) & 1u) << 3);
-        uint32_t cur;
-        if constexpr (J <= 28) cur = (S_lo >> J) & 0xFu;
-        else cur = funnel(S_hi, S_lo, J) & 0xFu;
-        const bool take = (uint32_t)J < ncols && popc(V) < popc(cur);
-        if constexpr (J <= 28) {
-            const uint32_t nlo = (S_lo & ~(0xFu << J)) | (V << J);
-            S_lo = take ? nlo : S_lo;
-        } else {
-            const uint32_t nlo = (S_lo & ~(0xFu << J)) | (V << J);
-            const uint32_t nhi = (S_hi & ~(0xFu >> (32 - J))) | (V >> (32 - J));
-            S_lo = take ? nlo : S_lo;
-            S_hi = take ? nhi : S_hi;
-        }
-        shouji_store<J + 1>(bs, S_lo, S_hi, ncols);
-    }
-}
-
-template <int EMAX, int I = 0>
-__device__ __forceinline__ void build_both(const WindowWords& q, uint32_t* Mh, uint32_t* G) {
-    if constexpr (I < 2 * EMAX + 1) {
-        diag_both<I - EMAX>(q, Mh[I], G[I]);
-        build_both<EMAX, I + 1>(q, Mh, G);
-    }
-}
-
 template <int EMAX, bool GENERAL>
-__device__ void whole_tile(const FilterParams& P, uint64_t tile, int lane, uint64_t* rdL,
-                           uint64_t* rfL) {
-    constexpr int D = 2 * EMAX + 1;
-    using DT = typename DeadMask<EMAX>::T;
-    uint64_t off;
-    const PairSlot ps = load_slot<GENERAL>(P, tile, lane, off);
-    stage_tile<GENERAL>(P, tile, lane, ps, off, rdL, rfL);
-
-    const bool doSS = P.filters & PAF_SNEAKYSNAKE;
-    const bool doGK = P.filters & PAF_GATEKEEPER;
-    const bool doSH = P.filters & PAF_SHOUJI;
-    const uint32_t m = ps.m, E = ps.E;
-    const bool mask_E = GENERAL ? (P.E != nullptr || P.uniform_E < (uint32_t)EMAX)
-                                : (P.uniform_E < (uint32_t)EMAX);
-
-    Snake z{0u, 0u, ps.valid && doSS, false, 0u};
-    bool cont = false;
-    DT dead = 0;
-    uint32_t gk_ham = 0, gk_cnt = 0;
-    uint32_t S_lo = ~0u, S_hi = ~0u, sh_cnt = 0;
-
-    uint32_t Mc[D], Gc[D], Gp[D];
-    if (ps.valid) {
-        const WindowWords q = window_words(rdL, rfL, lane, 0, P.wmax, (int)m);
-        build_both<EMAX>(q, Mc, Gc);
-    }
-#pragma unroll
-    for (int i = 0; i < D; ++i) Gp[i] = 0u;
-    if (mask_E && ps.valid) {
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            const int d = i - EMAX;
-            if ((uint32_t)(d < 0 ? -d : d) > E) { Mc[i] = ~0u; Gc[i] = ~0u; Gp[i] = ~0u; }
-        }
-    }
-
-    for (uint32_t w = 0; wave_any(ps.valid && w < ps.W); ++w) {
-        const bool have = ps.valid && w < ps.W;
-        if (have) {
-            const uint32_t colpast = vacant_word((int)w, (int)m);  // columns >= m
-            // SneakySnake on this window.
-            if (doSS && z.act) snake_window<EMAX, DT>(z, Mc, w, m, E, cont, dead);
-            if (doGK) gk_ham += popc(Mc[EMAX] & ~colpast);
-            // Next window's maps, then GateKeeper and Shouji per diagonal.
-            const WindowWords qn = window_words(rdL, rfL, lane, (int)w + 1, P.wmax, (int)m);
-            uint32_t Fw = ~0u;
-            ShoujiBest bs;
-            uint32_t Mn[D], Gn[D];
-            build_both<EMAX>(qn, Mn, Gn);
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                if (mask_E) {
-                    const int d = i - EMAX;
-                    if ((uint32_t)(d < 0 ? -d : d) > E) { Mn[i] = ~0u; Gn[i] = ~0u; }
-                }
-                if (doGK) Fw &= amend_word(Gc[i], Gp[i], Gn[i]);
-                if (doSH) shouji_candidate(bs, Mc[i], Mn[i], i == 0);
-                Gp[i] = Gc[i];
-                Gc[i] = Gn[i];
-                Mc[i] = Mn[i];
-            }
-            if (doGK) gk_cnt += popc(Fw & ~colpast);
-            if (doSH) {
-                const uint32_t ncols = m - 32u * w;  // >= 1
-                shouji_store(bs, S_lo, S_hi, ncols);
-                sh_cnt += popc(S_lo & ~colpast);
-                S_lo = S_hi;
-                S_hi = ~0u;
-            }
-        }
-    }
-
-    const bool gk_acc = gk_ham <= E || gk_cnt <= E;
-    const uint32_t gk_out = gk_ham <= E ? gk_ham : gk_cnt;
-    const bool sh_acc = sh_cnt <= E;
-    bool accs[3] = {z.acc, gk_acc, sh_acc};
-    uint32_t cnts[3] = {z.cnt, gk_out, sh_cnt};
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        if (!(P.filters & (1u << f))) continue;
-        if (GENERAL && P.perm) {
-            if (ps.in_batch) P.cnt[f][ps.id] = (uint16_t)(ps.valid ? cnts[f] : 0u);
-        } else {
-            const uint64_t bal = __ballot(ps.valid && accs[f]);
-            if (ps.in_batch) P.cnt[f][ps.slot] = (uint16_t)(ps.valid ? cnts[f] : 0u);
-            if (lane == 0) {
-                P.acc[f][2 * tile] = (uint32_t)bal;
-                if (tile * 64 + 32 < P.n_pairs) P.acc[f][2 * tile + 1] = (uint32_t)(bal >> 32);
-            }
-        }
-    }
-}
-
-template <Engine ENG, int EMAX, bool GENERAL>
-__global__ void __launch_bounds__(ENG == Engine::Snake ? 512 : 256) filter_kernel(FilterParams P) {
+__global__ void __launch_bounds__(512) snake_kernel(FilterParams P) {
     extern __shared__ uint64_t lds[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     uint64_t* rdL = lds + (size_t)wave * 2 * P.wmax * kLdsRow;
     uint64_t* rfL = rdL + (size_t)P.wmax * kLdsRow;
-    auto run = [&](uint64_t tile) {
-        if constexpr (ENG == Engine::Snake) snake_tile<EMAX, GENERAL>(P, tile, lane, rdL, rfL);
-        else whole_tile<EMAX, GENERAL>(P, tile, lane, rdL, rfL);
-    };
-    if (P.queue == nullptr) {
-        const uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-        if (tile < P.n_tiles) run(tile);
-        return;
-    }
-    // Persistent: each wave takes `grab` tiles at a time from the queue until
-    // it runs dry; every wave leaves after its first empty take.  The next
-    // take is issued before the current tiles are processed, so the queue's
-    // round trip overlaps the work.
-    uint32_t t0 = 0;
-    if (lane == 0) t0 = atomicAdd(P.queue, P.grab);
-    t0 = __shfl(t0, 0);
-    while (t0 < P.n_tiles) {
-        uint32_t nx = 0;
-        if (lane == 0) nx = atomicAdd(P.queue, P.grab);
-        const uint32_t t1 = min(P.n_tiles, t0 + P.grab);
-        for (uint32_t t = t0; t < t1; ++t) {
-            run(t);
-            wave_lds_sync();
-        }
-        t0 = __shfl(nx, 0);
-    }
+    for_each_tile(P, lane, wave, [&](uint64_t tile) { snake_tile<EMAX, GENERAL>(P, tile, lane, rdL, rfL); });
 }
 
-constexpr int kEmaxList[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 15, 20, 25, 31};
-
-template <Engine ENG, bool GENERAL>
-const void* kernel_for(int emax) {
+template <bool GENERAL>
+const void* snake_kernel_for(int emax) {
     switch (emax) {
 #define PAF_CASE(X) \
-    case X: return reinterpret_cast<const void*>(&filter_kernel<ENG, X, GENERAL>);
+    case X: return reinterpret_cast<const void*>(&snake_kernel<X, GENERAL>);
         PAF_CASE(0) PAF_CASE(1) PAF_CASE(2) PAF_CASE(3) PAF_CASE(4) PAF_CASE(5) PAF_CASE(6)
         PAF_CASE(7) PAF_CASE(8) PAF_CASE(10) PAF_CASE(12) PAF_CASE(15) PAF_CASE(20) PAF_CASE(25)
         PAF_CASE(31)
@@ -1001,11 +596,10 @@ int emax_bucket(int max_E) {
     return -1;
 }
 
-const void* filter_kernel_ptr(Engine eng, bool general, int emax) {
+const void* filter_kernel_ptr(Engine eng, bool general, int emax, uint32_t filters) {
     if (eng == Engine::Chunk) return general ? chunk_kernel_for<true>(emax) : chunk_kernel_for<false>(emax);
-    if (eng == Engine::Snake)
-        return general ? kernel_for<Engine::Snake, true>(emax) : kernel_for<Engine::Snake, false>(emax);
-    return general ? kernel_for<Engine::Whole, true>(emax) : kernel_for<Engine::Whole, false>(emax);
+    if (eng == Engine::Snake) return general ? snake_kernel_for<true>(emax) : snake_kernel_for<false>(emax);
+    return whole_kernel_ptr(general, emax, filters);
 }
 
 size_t filter_lds_bytes(uint32_t waves_per_block, uint32_t wmax) {
@@ -1019,7 +613,7 @@ size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_
 
 hipError_t launch_filter(const FilterParams& p, Engine eng, bool general, int emax,
                          const LaunchShape& shape, hipStream_t stream) {
-    const void* k = filter_kernel_ptr(eng, general, emax);
+    const void* k = filter_kernel_ptr(eng, general, emax, p.filters);
     if (!k) return hipErrorInvalidValue;
     FilterParams arg = p;
     void* args[] = {&arg};

@@ -76,7 +76,8 @@ hipError_t launch_accept_from_counts(const uint16_t* cnt, const uint16_t* len, u
                                      const uint8_t* E, uint32_t uniform_E, uint32_t max_len,
                                      uint32_t max_E, uint64_t n, uint32_t* acc, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
-const void* filter_kernel_ptr(Engine eng, bool general, int emax);
+const void* filter_kernel_ptr(Engine eng, bool general, int emax, uint32_t filters);
+const void* whole_kernel_ptr(bool general, int emax, uint32_t filters);
 size_t filter_lds_bytes(uint32_t waves_per_block, uint32_t wmax);
 size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_t chunk_tiles);
 

@@ -1,0 +1,273 @@
+// Whole-map decision stages for gfx950: GateKeeper (Ch. 5) and Shouji
+// (Ch. 6), which read every window of the map, plus SneakySnake on the same
+// map when asked for.  One lane per pair, 64 pairs per wave staged in LDS
+// (word-major); windows are walked in step.
+#include "paf_tile.h"
+
+namespace paf {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Whole-map engine.
+
+// GateKeeper's amendment of one window word (Ch. 5, Sec. 5.2.2; SRS of
+// Sec. 3.2.1): a zero inside a streak of one or two zeros bounded by ones on
+// both sides becomes one.  L1/L2 are the bits one/two columns to the left,
+// R1/R2 to the right (taken from the neighbouring windows).
+__device__ __forceinline__ uint32_t amend_word(uint32_t g, uint32_t prev, uint32_t next) {
+    const uint32_t L1 = funnel(g, prev, 31);
+    const uint32_t L2 = funnel(g, prev, 30);
+    const uint32_t R1 = funnel(next, g, 1);
+    const uint32_t R2 = funnel(next, g, 2);
+    return g | (L1 & (R1 | R2)) | (R1 & (L1 | L2));
+}
+
+// Shouji: bit-sliced best 4-column segment per window start column.
+struct ShoujiBest {
+    uint32_t o0, o1, o2;      // ones in the best segment (bit-sliced, 0..4)
+    uint32_t b0, b1, b2, b3;  // the best segment's bits
+};
+
+__device__ __forceinline__ void shouji_candidate(ShoujiBest& bs, uint32_t cur, uint32_t nxt,
+                                                 bool first) {
+    const uint32_t B0 = cur;
+    const uint32_t B1 = funnel(nxt, cur, 1);
+    const uint32_t B2 = funnel(nxt, cur, 2);
+    const uint32_t B3 = funnel(nxt, cur, 3);
+    const uint32_t s01 = B0 ^ B1, c01 = B0 & B1, s23 = B2 ^ B3, c23 = B2 & B3;
+    const uint32_t o0 = s01 ^ s23;
+    const uint32_t cm = s01 & s23;
+    const uint32_t o1 = c01 ^ c23 ^ cm;
+    const uint32_t o2 = c01 & c23;
+    if (first) {
+        bs = {o0, o1, o2, B0, B1, B2, B3};
+        return;
+    }
+    // Fewer ones wins; on a tie, a segment that starts with a zero beats one
+    // that does not; otherwise the earlier diagonal is kept.
+    const uint32_t t0 = ~o0 & bs.o0;
+    const uint32_t e1 = ~(o1 ^ bs.o1);
+    const uint32_t t1 = (~o1 & bs.o1) | (e1 & t0);
+    const uint32_t e2 = ~(o2 ^ bs.o2);
+    const uint32_t lt = (~o2 & bs.o2) | (e2 & t1);
+    const uint32_t eq = e2 & e1 & ~(o0 ^ bs.o0);
+    const uint32_t rep = lt | (eq & ~B0 & bs.b0);
+    bs.o0 = (rep & o0) | (~rep & bs.o0);
+    bs.o1 = (rep & o1) | (~rep & bs.o1);
+    bs.o2 = (rep & o2) | (~rep & bs.o2);
+    bs.b0 = (rep & B0) | (~rep & bs.b0);
+    bs.b1 = (rep & B1) | (~rep & bs.b1);
+    bs.b2 = (rep & B2) | (~rep & bs.b2);
+    bs.b3 = (rep & B3) | (~rep & bs.b3);
+}
+
+// Sequential store into the Shouji bit-vector for the 32 windows starting in
+// this window (Sec. 6.2.2): the best segment overwrites the vector's four
+// bits when it holds strictly more zeros.  S covers columns [32w, 32w+64).
+template <int J = 0>
+__device__ __forceinline__ void shouji_store(const ShoujiBest& bs, uint32_t& S_lo, uint32_t& S_hi,
+                                             uint32_t ncols) {
+    if constexpr (J < 32) {
+        const uint32_t V = ((bs.b0 >> J) & 1u) | (((bs.b1 >> J) & 1u) << 1) |
+                           (((bs.b2 >> J) & 1u) << 2) | (((bs.b3 >> J) & 1u) << 3);
+        uint32_t cur;
+        if constexpr (J <= 28) cur = (S_lo >> J) & 0xFu;
+        else cur = funnel(S_hi, S_lo, J) & 0xFu;
+        const bool take = (uint32_t)J < ncols && popc(V) < popc(cur);
+        if constexpr (J <= 28) {
+            const uint32_t nlo = (S_lo & ~(0xFu << J)) | (V << J);
+            S_lo = take ? nlo : S_lo;
+        } else {
+            const uint32_t nlo = (S_lo & ~(0xFu << J)) | (V << J);
+            const uint32_t nhi = (S_hi & ~(0xFu >> (32 - J))) | (V >> (32 - J));
+            S_lo = take ? nlo : S_lo;
+            S_hi = take ? nhi : S_hi;
+        }
+        shouji_store<J + 1>(bs, S_lo, S_hi, ncols);
+    }
+}
+
+template <int EMAX, int I = 0>
+__device__ __forceinline__ void build_both(const WindowWords& q, uint32_t* Mh, uint32_t* G) {
+    if constexpr (I < 2 * EMAX + 1) {
+        diag_both<I - EMAX>(q, Mh[I], G[I]);
+        build_both<EMAX, I + 1>(q, Mh, G);
+    }
+}
+
+// Only the blocked map (SneakySnake, Shouji): vacant and past-end cells 1.
+template <int EMAX, int I = 0>
+__device__ __forceinline__ void build_blocked(const WindowWords& q, uint32_t* Mh) {
+    if constexpr (I < 2 * EMAX + 1) {
+        constexpr int d = I - EMAX;
+        Mh[I] = diag_raw<d>(q) | diag_vacant<d>(q) | q.vc;
+        build_blocked<EMAX, I + 1>(q, Mh);
+    }
+}
+
+// Only GateKeeper's map: vacant and past-end cells 0.
+template <int EMAX, int I = 0>
+__device__ __forceinline__ void build_gk(const WindowWords& q, uint32_t* G) {
+    if constexpr (I < 2 * EMAX + 1) {
+        constexpr int d = I - EMAX;
+        G[I] = diag_raw<d>(q) & ~(diag_vacant<d>(q) | q.vc);
+        build_gk<EMAX, I + 1>(q, G);
+    }
+}
+
+// FS: the decision stages this instantiation runs (bits of PAF_*), or 0 for
+// any mask given at run time.  Only the words the stages read are built.
+template <int EMAX, bool GENERAL, int FS>
+__device__ void whole_tile(const FilterParams& P, uint64_t tile, int lane, uint64_t* rdL,
+                           uint64_t* rfL) {
+    constexpr int D = 2 * EMAX + 1;
+    using DT = typename DeadMask<EMAX>::T;
+    uint64_t off;
+    const PairSlot ps = load_slot<GENERAL>(P, tile, lane, off);
+    stage_tile<GENERAL>(P, tile, lane, ps, off, rdL, rfL);
+
+    constexpr bool RT = FS == 0;
+    constexpr bool needG = RT || (FS & PAF_GATEKEEPER);
+    constexpr bool needM = RT || (FS & (PAF_SNEAKYSNAKE | PAF_SHOUJI));
+    const bool doSS = RT ? (P.filters & PAF_SNEAKYSNAKE) != 0 : (FS & PAF_SNEAKYSNAKE) != 0;
+    const bool doGK = RT ? (P.filters & PAF_GATEKEEPER) != 0 : (FS & PAF_GATEKEEPER) != 0;
+    const bool doSH = RT ? (P.filters & PAF_SHOUJI) != 0 : (FS & PAF_SHOUJI) != 0;
+    const uint32_t m = ps.m, E = ps.E;
+    const bool mask_E = GENERAL ? (P.E != nullptr || P.uniform_E < (uint32_t)EMAX)
+                                : (P.uniform_E < (uint32_t)EMAX);
+
+    Snake z{0u, 0u, ps.valid && doSS, false, 0u};
+    bool cont = false;
+    DT dead = 0;
+    uint32_t gk_ham = 0, gk_cnt = 0;
+    uint32_t S_lo = ~0u, S_hi = ~0u, sh_cnt = 0;
+
+    uint32_t Mc[needM ? D : 1], Gc[needG ? D : 1], Gp[needG ? D : 1];
+    if (ps.valid) {
+        const WindowWords q = window_words(rdL, rfL, lane, 0, P.wmax, (int)m);
+        if constexpr (needM && needG) build_both<EMAX>(q, Mc, Gc);
+        else if constexpr (needM) build_blocked<EMAX>(q, Mc);
+        else build_gk<EMAX>(q, Gc);
+    }
+    if constexpr (needG) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) Gp[i] = 0u;
+    }
+    if (mask_E && ps.valid) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int d = i - EMAX;
+            if ((uint32_t)(d < 0 ? -d : d) > E) {
+                if constexpr (needM) Mc[i] = ~0u;
+                if constexpr (needG) { Gc[i] = ~0u; Gp[i] = ~0u; }
+            }
+        }
+    }
+
+    for (uint32_t w = 0; wave_any(ps.valid && w < ps.W); ++w) {
+        const bool have = ps.valid && w < ps.W;
+        if (have) {
+            const uint32_t colpast = vacant_word((int)w, (int)m);  // columns >= m
+            // SneakySnake on this window.
+            if constexpr (needM)
+                if (doSS && z.act) snake_window<EMAX, DT>(z, Mc, w, m, E, cont, dead);
+            // GateKeeper's fast path: Hamming distance on diagonal 0 (its
+            // mismatches, vacant cells not counted).
+            if constexpr (needG)
+                if (doGK) gk_ham += popc(Gc[EMAX] & ~colpast);
+            // Next window's maps, then GateKeeper and Shouji per diagonal.
+            const WindowWords qn = window_words(rdL, rfL, lane, (int)w + 1, P.wmax, (int)m);
+            uint32_t Fw = ~0u;
+            ShoujiBest bs;
+            uint32_t Mn[needM ? D : 1], Gn[needG ? D : 1];
+            if constexpr (needM && needG) build_both<EMAX>(qn, Mn, Gn);
+            else if constexpr (needM) build_blocked<EMAX>(qn, Mn);
+            else build_gk<EMAX>(qn, Gn);
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                if (mask_E) {
+                    const int d = i - EMAX;
+                    if ((uint32_t)(d < 0 ? -d : d) > E) {
+                        if constexpr (needM) Mn[i] = ~0u;
+                        if constexpr (needG) Gn[i] = ~0u;
+                    }
+                }
+                if constexpr (needG) {
+                    if (doGK) Fw &= amend_word(Gc[i], Gp[i], Gn[i]);
+                    Gp[i] = Gc[i];
+                    Gc[i] = Gn[i];
+                }
+                if constexpr (needM) {
+                    if (doSH) shouji_candidate(bs, Mc[i], Mn[i], i == 0);
+                    Mc[i] = Mn[i];
+                }
+            }
+            if (doGK) gk_cnt += popc(Fw & ~colpast);
+            if (doSH) {
+                const uint32_t ncols = m - 32u * w;  // >= 1
+                shouji_store(bs, S_lo, S_hi, ncols);
+                sh_cnt += popc(S_lo & ~colpast);
+                S_lo = S_hi;
+                S_hi = ~0u;
+            }
+        }
+    }
+
+    const bool gk_acc = gk_ham <= E || gk_cnt <= E;
+    const uint32_t gk_out = gk_ham <= E ? gk_ham : gk_cnt;
+    const bool sh_acc = sh_cnt <= E;
+    bool accs[3] = {z.acc, gk_acc, sh_acc};
+    uint32_t cnts[3] = {z.cnt, gk_out, sh_cnt};
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        if (!(P.filters & (1u << f))) continue;
+        if (GENERAL && P.perm) {
+            if (ps.in_batch) P.cnt[f][ps.id] = (uint16_t)(ps.valid ? cnts[f] : 0u);
+        } else {
+            const uint64_t bal = __ballot(ps.valid && accs[f]);
+            if (ps.in_batch) P.cnt[f][ps.slot] = (uint16_t)(ps.valid ? cnts[f] : 0u);
+            if (lane == 0) {
+                P.acc[f][2 * tile] = (uint32_t)bal;
+                if (tile * 64 + 32 < P.n_pairs) P.acc[f][2 * tile + 1] = (uint32_t)(bal >> 32);
+            }
+        }
+    }
+}
+
+
+template <int EMAX, bool GENERAL, int FS>
+__global__ void __launch_bounds__(256) whole_kernel(FilterParams P) {
+    extern __shared__ uint64_t lds[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    uint64_t* rdL = lds + (size_t)wave * 2 * P.wmax * kLdsRow;
+    uint64_t* rfL = rdL + (size_t)P.wmax * kLdsRow;
+    for_each_tile(P, lane, wave, [&](uint64_t tile) { whole_tile<EMAX, GENERAL, FS>(P, tile, lane, rdL, rfL); });
+}
+
+template <bool GENERAL, int FS>
+const void* whole_for(int emax) {
+    switch (emax) {
+#define PAF_CASE(X) \
+    case X: return reinterpret_cast<const void*>(&whole_kernel<X, GENERAL, FS>);
+        PAF_CASE(0) PAF_CASE(1) PAF_CASE(2) PAF_CASE(3) PAF_CASE(4) PAF_CASE(5) PAF_CASE(6)
+        PAF_CASE(7) PAF_CASE(8) PAF_CASE(10) PAF_CASE(12) PAF_CASE(15) PAF_CASE(20) PAF_CASE(25)
+        PAF_CASE(31)
+#undef PAF_CASE
+        default: return nullptr;
+    }
+}
+
+}  // namespace
+
+// GateKeeper alone and Shouji alone get kernels of their own; every other
+// mask runs on the kernel that reads the mask at run time.
+const void* whole_kernel_ptr(bool general, int emax, uint32_t filters) {
+    if (filters == PAF_GATEKEEPER) return general ? whole_for<true, PAF_GATEKEEPER>(emax)
+                                                  : whole_for<false, PAF_GATEKEEPER>(emax);
+    if (filters == PAF_SHOUJI) return general ? whole_for<true, PAF_SHOUJI>(emax) : whole_for<false, PAF_SHOUJI>(emax);
+    return general ? whole_for<true, 0>(emax) : whole_for<false, 0>(emax);
+}
+
+}  // namespace paf
