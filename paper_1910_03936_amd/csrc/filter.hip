@@ -74,11 +74,16 @@ __device__ void snake_tile(const FilterParams& P, uint64_t tile, int lane, uint6
             bool inw = c < wend;
             while (inw) {
                 const uint32_t s = c - w0;
-                uint32_t best = 0;
+                const uint32_t bs = 1u << s;
+                uint32_t r0 = 0, r1 = 0;
 #pragma unroll
-                for (int i = 0; i < D; ++i) best = max(best, ffbl(M[i] >> s));
-                const bool clear = best == 0xFFFFFFFFu;   // a pipe runs past the window
-                const uint32_t R = clear ? wend : c + best;
+                for (int i = 0; i < D; i += 2) {
+                    r0 = pipe_runs(r0, M[i], bs);
+                    if (i + 1 < D) r1 = pipe_runs(r1, M[i + 1], bs);
+                }
+                const uint32_t runs = r0 | r1;
+                const bool clear = (int32_t)runs < 0;      // a pipe runs past the window
+                const uint32_t R = clear ? wend : c + popc(runs);
                 const bool reach = R >= m;                 // the pipe reaches the last column
                 const bool obst = !reach && !clear;
                 e += obst ? 1u : 0u;
@@ -160,10 +165,6 @@ __device__ __forceinline__ uint32_t or_xor3(uint32_t a, uint32_t t, uint32_t b) 
 }
 __device__ __forceinline__ uint32_t nor_xor3(uint32_t a, uint32_t t, uint32_t b) {
     return __builtin_amdgcn_bitop3_b32(a, t, b, 0x21);
-}
-// acc | (z & ~y) in one instruction (truth table 0xF4 with s0 = acc).
-__device__ __forceinline__ uint32_t or_andn(uint32_t acc, uint32_t z, uint32_t y) {
-    return __builtin_amdgcn_bitop3_b32(acc, z, y, 0xF4);
 }
 
 template <int EMAX, bool VAC, bool CONT, typename DT, int I = 0>

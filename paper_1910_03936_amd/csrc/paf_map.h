@@ -14,15 +14,22 @@ __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t s)
     return __builtin_amdgcn_alignbit(hi, lo, s);
 }
 
-// Index of the lowest set bit; 0xFFFFFFFF for 0 (the hardware's own
-// convention, which the probe relies on: a clear diagonal wins every max).
-__device__ __forceinline__ uint32_t ffbl(uint32_t x) {
-    uint32_t r;
-    asm("v_ffbl_b32 %0, %1" : "=v"(r) : "v"(x));
-    return r;
+__device__ __forceinline__ uint32_t popc(uint32_t x) { return __builtin_popcount(x); }
+
+// acc | (z & ~y) in one v_bitop3 (truth table 0xF4 with s0 = acc, s1 = z,
+// s2 = y).
+__device__ __forceinline__ uint32_t or_andn(uint32_t acc, uint32_t z, uint32_t y) {
+    return __builtin_amdgcn_bitop3_b32(acc, z, y, 0xF4);
 }
 
-__device__ __forceinline__ uint32_t popc(uint32_t x) { return __builtin_popcount(x); }
+// Free cells from window-relative column s on, given a mismatch word M
+// (1 = blocked): subtracting 1 << s borrows through the zeros of M from s up
+// to its next one, so (M - (1 << s)) & ~M is exactly that run of free cells
+// (all of [s, 32) when no obstacle follows).  Accumulated over diagonals, the
+// OR is [s, s + depth of the deepest pipe).
+__device__ __forceinline__ uint32_t pipe_runs(uint32_t acc, uint32_t M, uint32_t bs) {
+    return or_andn(acc, M - bs, M);
+}
 
 // Read positions 32k..32k+31 that fall outside [0, m): a vacant map cell.
 __device__ __forceinline__ uint32_t vacant_word(int k, int m) {

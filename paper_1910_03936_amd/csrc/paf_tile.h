@@ -159,15 +159,17 @@ __device__ __forceinline__ void snake_window(Snake& z, const uint32_t* M, uint32
     const uint32_t wend = 32u * (w + 1);
     while (z.act && z.c < wend) {
         const uint32_t s = z.c - 32u * w;
-        uint32_t best = 0;
+        const uint32_t bs = 1u << s;
+        uint32_t runs = 0;
         if (cont) {
-            // s == 0 here.
+            // s == 0 here; dead diagonals are blocked in the first column.
 #pragma unroll
-            for (int i = 0; i < D; ++i) best = max(best, ffbl(M[i] | (uint32_t)((dead >> i) & 1u)));
+            for (int i = 0; i < D; ++i) runs = pipe_runs(runs, M[i] | (uint32_t)((dead >> i) & 1u), bs);
         } else {
 #pragma unroll
-            for (int i = 0; i < D; ++i) best = max(best, ffbl(M[i] >> s));
+            for (int i = 0; i < D; ++i) runs = pipe_runs(runs, M[i], bs);
         }
+        const uint32_t best = (int32_t)runs < 0 ? 0xFFFFFFFFu : popc(runs);
         if (best == 0xFFFFFFFFu) {
             // Some pipe runs past the window's end.
             if (wend >= m) {
