@@ -99,7 +99,7 @@ const char* paf_last_error(void);
  * threshold outside its batch's bounds. */
 paf_status paf_check(paf_ctx* ctx, void* stream);
 
-/* Step a1 -- encode (Ch. 4 host read encoder; Ch. 5 Method 3).
+/* Encoder (Ch. 4 host read encoder; Ch. 5 Method 3).
  * codes [device]: n rows of code_stride bytes, base values 0..3 (A,C,G,T);
  * row p holds m(p) bases (len/uniform_len as in paf_batch).
  * words [device]: output, written at off(p) as in paf_batch; the caller
@@ -115,7 +115,7 @@ paf_status paf_pack_host(const uint8_t* codes, uint32_t code_stride, const uint1
                          uint16_t uniform_len, const uint64_t* word_offset, uint32_t stride_words,
                          uint64_t n, uint64_t* words, int threads);
 
-/* Steps a2-a7 -- plain batched filter.  For every pair: stage its words,
+/* Plain batched filter.  For every pair: stage its words,
  * build the 2E+1 diagonal match bit-vectors (neighbourhood map, Eq. 6.1 /
  * unweighted maze, Eq. 8.2) and run the requested decision stages on them:
  * SneakySnake's greedy traversal (Ch. 8, Sec. 8.4), GateKeeper's Hamming
@@ -129,17 +129,21 @@ paf_status paf_pack_host(const uint8_t* codes, uint32_t code_stride, const uint1
 paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, const paf_out* out,
                       void* stream);
 
-/* Step a8 -- the same filter as one persistent launch over a work queue of
- * 64-pair tiles (the Read Controller's role, Sec. 4.2.1), for batches of
- * uneven lengths and per-pair thresholds.  The launch (queue reset + kernel)
- * is captured once into a HIP graph per (layout, filters, bounds, stream)
- * and replayed; the layout is the one paf_autotune chose for this batch's
- * (max_len, max_E, filters) class, else the default.  Outputs as
- * paf_filter. */
+/* Persistent launch: the same filter as one launch over 64-pair tiles, or
+ * over compacting chunks of tiles for SneakySnake alone, handed out by a work
+ * queue (the Read Controller's role, Sec. 4.2.1) or by the hardware
+ * dispatcher as a full grid, for batches of uneven lengths and per-pair
+ * thresholds.  The launch (queue reset + kernel) is captured once into a HIP
+ * graph per (layout, filters, bounds, stream) and replayed; the layout is the
+ * forced one, else the one paf_autotune chose for this batch's (max_len,
+ * max_E, filters) class, else the default (per-tile engine, work queue of
+ * 4 waves x 4 blocks per CU, 2 tiles per take).  Outputs as paf_filter. */
 paf_status paf_filter_persistent(paf_ctx* ctx, const paf_batch* batch, uint32_t filters,
                                  const paf_out* out, void* stream);
 
-/* Layout of the persistent filter. */
+/* Launch layout of the persistent, ordered and learned launches (paf_filter
+ * takes waves_per_block, chunk_tiles and the pass widths from a forced
+ * layout). */
 typedef struct {
     uint32_t lanes_per_pair;   /* 1 (pair per lane) */
     uint32_t waves_per_block;  /* 1, 2, 4 or 8 */
@@ -163,7 +167,7 @@ paf_status paf_autotune(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, 
                         void* stream, paf_layout* chosen, float* best_ms, float* default_ms);
 paf_status paf_set_layout(paf_ctx* ctx, const paf_layout* layout); /* NULL = back to autotuned */
 
-/* Step a9 -- learned cost bucketing.
+/* Learned cost bucketing.
  * Features of each pair (fp32, 64 per pair, row-major [n][64]): [0] = m/512,
  * [1] = E/32, slot 32+d = fraction of matching map cells over the first
  * min(m, 64) columns of diagonal d, |d| <= min(E, 30); other slots 0. */
@@ -232,32 +236,34 @@ paf_status paf_filter_ordered(paf_ctx* ctx, const paf_batch* batch, uint32_t fil
 paf_status paf_filter_bucketed(paf_ctx* ctx, const paf_batch* batch, uint32_t filters,
                                const paf_out* out, void* stream);
 
-/* Step a9, chunk-local bucketing, stage 1: features and cost model of every
+/* Chunk-local learned bucketing, stage 1: features and cost model of every
  * pair; key[p] = 15 - level, level = min(15, floor(clamp(y, 0, 32) / 2)),
  * y the predicted SneakySnake count at E = 31 (key: uint8 [device],
  * n_pairs entries, original order). */
 paf_status paf_cost_levels(paf_ctx* ctx, const paf_batch* batch, uint8_t* key, void* stream);
 
 /* Stage 2: SneakySnake alone on the compacting engine, the pairs of each
- * chunk entering its first window in ascending key order (key: uint8 per
- * pair [device], original order, used modulo 16).  Any key gives the
- * outputs of paf_filter; a key that groups pairs of like cost makes the
- * launch faster.  Layout as paf_filter_bucketed_local. */
+ * chunk entering the first pass grouped into four classes by bits 2-3 of
+ * their key (key: uint8 per pair [device], original order; class = (key &
+ * 15) >> 2, class 0 first; the two pairs sharing a 128-byte line of sequence
+ * words take the lower class of the two).  Any key gives the outputs of
+ * paf_filter; a key that groups pairs of like cost makes the groups of 64
+ * more even.  Layout as paf_filter_bucketed_local. */
 paf_status paf_filter_keyed(paf_ctx* ctx, const paf_batch* batch, const uint8_t* key, const paf_out* out,
                             void* stream);
 
-/* Step a9, chunk-local bucketing (SneakySnake alone).  The cost model's
+/* Chunk-local learned bucketing (SneakySnake alone).  The cost model's
  * prediction puts every pair on one of 16 levels (width 2 obstacles, highest
- * first).  The compacting filter then sorts the pairs of each of its chunks
- * by level before the first window, so each pass of 64 takes pairs of like
- * cost, while the pairs stay in place in memory (no global permutation, no
- * gathers).  Model and filter are captured in one HIP graph per (batch,
+ * first).  The compacting filter then groups the pairs of each of its chunks
+ * into four classes of four levels before the first window (paf_filter_keyed),
+ * so each group of 64 takes pairs of like cost, while the pairs stay in place
+ * in memory (no global permutation, no gathers).  Model and filter are captured in one HIP graph per (batch,
  * layout, outputs).  Outputs as paf_filter, in the original order.  The
  * launch layout is the forced or autotuned one if it has chunk_tiles > 0,
  * else paf_filter's. */
 paf_status paf_filter_bucketed_local(paf_ctx* ctx, const paf_batch* batch, const paf_out* out, void* stream);
 
-/* Step a11 -- streaming from host memory (the host-to-accelerator stream of
+/* Streaming from host memory (the host-to-accelerator stream of
  * Ch. 4, Secs. 4.2-4.4).  All pointers [host]; page-locked (pinned) memory
  * lets the copies overlap the filtering.  Pairs are stored back to back:
  * pair p's words start at word sum_{q<p} ceil(len[q] / 32) of reads and of
@@ -281,8 +287,9 @@ typedef struct {
 /* Filters every pair of a host batch, chunk_pairs pairs at a time (a positive
  * multiple of 64): each chunk is copied on a copy stream into one of two
  * device buffers while the previous chunk is filtered on a compute stream
- * (plain batching, or the learned pipeline of paf_filter_bucketed when
- * `learned` is nonzero), and its decisions are copied back into host_out
+ * (plain batching, or when `learned` is nonzero the learned pipeline:
+ * paf_filter_bucketed_local for SneakySnake alone, paf_filter_bucketed for
+ * other masks), and its decisions are copied back into host_out
  * (paf_out with [host] pointers: accept bits and counts for all n pairs).
  * Blocks until every chunk is done.  Decisions equal paf_filter's. */
 paf_status paf_stream_filter(paf_ctx* ctx, const paf_host_batch* batch, uint64_t chunk_pairs,

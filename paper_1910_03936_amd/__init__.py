@@ -201,7 +201,7 @@ class Context:
     def check(self, stream=None):
         _check(self.lib.paf_check(self.h, _stream(stream)))
 
-    # -- a1: encode -------------------------------------------------------
+    # -- encode -------------------------------------------------------------
     def pack(self, codes: torch.Tensor, lens: torch.Tensor | None = None, uniform_len: int = 0,
              word_offset: torch.Tensor | None = None, stride_words: int = 0, total_words: int = 0,
              stream=None) -> torch.Tensor:
@@ -236,7 +236,7 @@ class Context:
         return Batch(rd, rf, n, stride, None, lens, Es, uniform_len, uniform_E,
                      max_len or uniform_len or cs, max_E or uniform_E)
 
-    # -- a2..a7: filter ---------------------------------------------------
+    # -- filter ---------------------------------------------------------
     def alloc_out(self, n: int, filters: int, device) -> dict:
         out = {}
         for f in range(3):
@@ -286,7 +286,7 @@ class Context:
             lay = Layout(**layout)
             _check(self.lib.paf_set_layout(self.h, ctypes.byref(lay)))
 
-    # -- a9/a10: cost model ----------------------------------------------
+    # -- cost model --------------------------------------------------
     def features(self, batch: Batch, stream=None) -> torch.Tensor:
         f = torch.empty((batch.n_pairs, 64), dtype=torch.float32, device=batch.device)
         cb = batch.c()
