@@ -83,11 +83,12 @@ __device__ void snake_tile(const FilterParams& P, uint64_t tile, int lane, uint6
                 }
                 const uint32_t runs = r0 | r1;
                 const bool clear = (int32_t)runs < 0;      // a pipe runs past the window
-                const uint32_t R = clear ? wend : c + popc(runs);
+                // The obstacle's column (the window's end when clear).
+                const uint32_t R = c + popc(runs);
                 const bool reach = R >= m;                 // the pipe reaches the last column
                 const bool obst = !reach && !clear;
                 e += obst ? 1u : 0u;
-                c = reach ? c : (clear ? wend : R + 1u);
+                c = R + 1u + (uint32_t)((int32_t)runs >> 31);
                 const bool rej = e > E;
                 const bool fin_acc = reach || (obst && !rej && c >= m);
                 acc = fin_acc;
@@ -379,11 +380,15 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                     }
                     const uint32_t runs = r0 | r1;
                     const bool clear = (int32_t)runs < 0;
-                    const uint32_t R = clear ? wend : c + (uint32_t)__builtin_popcount(runs);
+                    // The obstacle's column; when a pipe runs past the window
+                    // the run is [s, 32) and this is the window's end.
+                    const uint32_t R = c + (uint32_t)__builtin_popcount(runs);
                     const bool reach = R >= m;
                     const bool obst = !reach && !clear;
                     e += obst ? 1u : 0u;
-                    c = reach ? c : (clear ? wend : R + 1u);
+                    // Cross the obstacle (R + 1), or stay at the window's end
+                    // inside the pipe (R); a lane that reached m is done.
+                    c = R + 1u + (uint32_t)((int32_t)runs >> 31);
                     const bool rej = e > E;
                     const bool fin_acc = reach || (obst && !rej && c >= m);
                     acc = fin_acc;
