@@ -62,15 +62,33 @@ __device__ __forceinline__ void shouji_candidate(ShoujiBest& bs, uint32_t cur, u
     bs.b3 = (rep & B3) | (~rep & bs.b3);
 }
 
+// Bits 0..7 of x spread to bits 0, 4, ..., 28.
+__device__ __forceinline__ uint32_t spread8(uint32_t x) {
+    x = (x | (x << 12)) & 0x000F000Fu;
+    x = (x | (x << 6)) & 0x03030303u;
+    return (x | (x << 3)) & 0x11111111u;
+}
+
+// The best segments of the window's 32 start columns as nibbles: word k holds
+// the segment of column j = 8k + i in bits 4i..4i+3 (bit t = the segment's
+// column j + t).
+__device__ __forceinline__ void shouji_nibbles(const ShoujiBest& bs, uint32_t* nib) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int sh = 8 * k;
+        nib[k] = spread8((bs.b0 >> sh) & 0xFFu) | (spread8((bs.b1 >> sh) & 0xFFu) << 1) |
+                 (spread8((bs.b2 >> sh) & 0xFFu) << 2) | (spread8((bs.b3 >> sh) & 0xFFu) << 3);
+    }
+}
+
 // Sequential store into the Shouji bit-vector for the 32 windows starting in
 // this window (Sec. 6.2.2): the best segment overwrites the vector's four
 // bits when it holds strictly more zeros.  S covers columns [32w, 32w+64).
 template <int J = 0>
-__device__ __forceinline__ void shouji_store(const ShoujiBest& bs, uint32_t& S_lo, uint32_t& S_hi,
-                                             uint32_t ncols) {
+__device__ __forceinline__ void shouji_store_nib(const uint32_t* nib, uint32_t& S_lo, uint32_t& S_hi,
+                                                 uint32_t ncols) {
     if constexpr (J < 32) {
-        const uint32_t V = ((bs.b0 >> J) & 1u) | (((bs.b1 >> J) & 1u) << 1) |
-                           (((bs.b2 >> J) & 1u) << 2) | (((bs.b3 >> J) & 1u) << 3);
+        const uint32_t V = (nib[J >> 3] >> (4 * (J & 7))) & 0xFu;
         uint32_t cur;
         if constexpr (J <= 28) cur = (S_lo >> J) & 0xFu;
         else cur = funnel(S_hi, S_lo, J) & 0xFu;
@@ -84,7 +102,7 @@ __device__ __forceinline__ void shouji_store(const ShoujiBest& bs, uint32_t& S_l
             S_lo = take ? nlo : S_lo;
             S_hi = take ? nhi : S_hi;
         }
-        shouji_store<J + 1>(bs, S_lo, S_hi, ncols);
+        shouji_store_nib<J + 1>(nib, S_lo, S_hi, ncols);
     }
 }
 
@@ -206,7 +224,9 @@ __device__ void whole_tile(const FilterParams& P, uint64_t tile, int lane, uint6
             if (doGK) gk_cnt += popc(Fw & ~colpast);
             if (doSH) {
                 const uint32_t ncols = m - 32u * w;  // >= 1
-                shouji_store(bs, S_lo, S_hi, ncols);
+                uint32_t nib[4];
+                shouji_nibbles(bs, nib);
+                shouji_store_nib(nib, S_lo, S_hi, ncols);
                 sh_cnt += popc(S_lo & ~colpast);
                 S_lo = S_hi;
                 S_hi = ~0u;
