@@ -336,7 +336,7 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
             const uint32_t E = t.E;
             const int W = (int)((m + 31) >> 5);
             uint32_t c = t.c, e = t.e;
-            bool cont = t.cont, acc = false;
+            bool cont = t.cont;
             for (uint32_t wk = w; wk < w + span && wave_any(act); ++wk) {
                 const WindowWords q = window_words_direct(P.reads + off, P.refs + off, (int)wk, W, (int)m);
                 // Vacant cells only occur in the first window and near the end.
@@ -359,19 +359,22 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                         if ((uint32_t)(dd < 0 ? -dd : dd) > E) M[d] = 0u;
                     }
                 }
-                const uint32_t w0 = 32u * wk, wend = w0 + 32u;
+                // The snake state stays in plain integers (column c, edits e,
+                // whether the last probe ran through the window's end and the
+                // bit it started from), so the loop carries no lane masks
+                // beyond its own condition: the lane probes while c is inside
+                // both the window and the pair and e <= E.
+                const uint32_t w0 = 32u * wk, w31 = w0 + 31u;
+                const uint32_t lim = min(m, w0 + 32u);
                 const bool live = act;
-                bool ncont = false;
-                uint32_t s_prev = 0;
-                bool inw = act && c < wend;
-                while (inw) {
+                uint32_t clear = 0, bs = 0;
+                while (act && (int32_t)((c - lim) & (e - E - 1u)) < 0) {
                     // Pipes from column c: adding 1 << s to a match word
                     // carries through its run of free cells from s, so
                     // Z & ~(Z + (1 << s)) is that run; the OR over the
                     // diagonals is [s, s + deepest run), with bit 31 set when a
                     // pipe reaches the window's end.
-                    const uint32_t s = c - w0;
-                    const uint32_t bs = 1u << s;
+                    bs = 0x80000000u >> (w31 - c);
                     uint32_t r0 = 0, r1 = 0;
 #pragma unroll
                     for (int d = 0; d < D; d += 2) {
@@ -379,53 +382,46 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                         if (d + 1 < D) r1 = or_andn(r1, M[d + 1], M[d + 1] + bs);
                     }
                     const uint32_t runs = r0 | r1;
-                    const bool clear = (int32_t)runs < 0;
+                    clear = runs >> 31;
                     // The obstacle's column; when a pipe runs past the window
                     // the run is [s, 32) and this is the window's end.
                     const uint32_t R = c + (uint32_t)__builtin_popcount(runs);
-                    const bool reach = R >= m;
-                    const bool obst = !reach && !clear;
-                    e += obst ? 1u : 0u;
+                    // An obstacle inside the pair (R < m) counts one edit.
+                    e += ((R - m) >> 31) & (clear ^ 1u);
                     // Cross the obstacle (R + 1), or stay at the window's end
-                    // inside the pipe (R); a lane that reached m is done.
-                    c = R + 1u + (uint32_t)((int32_t)runs >> 31);
-                    const bool rej = e > E;
-                    const bool fin_acc = reach || (obst && !rej && c >= m);
-                    acc = fin_acc;
-                    if (clear && !reach) {
-                        ncont = true;
-                        s_prev = s;
-                    }
-                    act = !(fin_acc || rej);
-                    inw = act && c < wend;
+                    // inside the pipe (R).
+                    c = R + 1u - clear;
                 }
-                if (live && !act) {
+                // A lane is decided once it crossed the pair's end (accept
+                // exactly when e <= E) or counted E + 1 edits.
+                if (live && (c >= m || e > E)) {
+                    act = false;
                     const uint64_t slot = slot0 + t.idx;
                     if (plain_out) {
                         P.cnt[0][slot] = (uint16_t)e;
-                        if (acc) atomicOr(&L.acc[t.idx >> 5], 1u << (t.idx & 31u));
+                        if (e <= E) atomicOr(&L.acc[t.idx >> 5], 1u << (t.idx & 31u));
                     } else {
                         P.cnt[0][P.perm[slot]] = (uint16_t)e;
                     }
                 }
+                const bool ncont = act && clear != 0u;
                 // A diagonal stays alive into the next window when its run
-                // from s_prev reaches this window's end, i.e. when adding
-                // 1 << s_prev to its match word carries out of bit 31.
+                // from the last probe's start reaches this window's end: bit
+                // 31 of Z & ~(Z + bs), shifted into the alive mask.
                 DT dm = 0;
-                if (wave_any(act && ncont)) {
-                    const uint32_t bs = 1u << s_prev;
+                if (wave_any(ncont)) {
                     uint32_t lo = 0, hi = 0;
 #pragma unroll
                     for (int d = D - 1; d >= 0; --d) {
-                        const uint32_t carry = (uint32_t)(((uint64_t)M[d] + bs) >> 32);
-                        if (d >= 32) hi = (hi << 1) | carry;
-                        else lo = (lo << 1) | carry;
+                        const uint32_t run = M[d] & ~(M[d] + bs);
+                        if (d >= 32) hi = funnel(hi, run, 31);
+                        else lo = funnel(lo, run, 31);
                     }
                     const DT alive = (DT)lo | (sizeof(DT) > 4 ? (DT)((uint64_t)hi << 32) : (DT)0);
                     constexpr DT all = (D >= 8 * (int)sizeof(DT)) ? ~(DT)0 : (((DT)1 << D) - 1);
                     dm = ~alive & all;
                 }
-                cont = act && ncont;
+                cont = ncont;
                 dead = cont ? dm : (DT)0;
             }
             // Survivors go on to the next pass.
