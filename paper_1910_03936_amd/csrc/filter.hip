@@ -157,10 +157,14 @@ __device__ __forceinline__ ChunkEntry chunk_unpack(uint64_t v) {
 // Match words of one window for the compacting engine: bit j of Z_d is 1
 // when column j is a free cell of diagonal d, i.e. the complement of the
 // mismatch word (lo ^ flo) | (hi ^ fhi) over the two code planes.  VAC folds
-// in the vacant cells (first and last windows), CONT the dead-diagonal bit of
-// a snake that entered inside a pipe (bit 0 of the window).  v_bitop3 takes
-// s1 | (s0 ^ s2) (truth table 0xDE) and its complement (0x21) in one
-// instruction; both are symmetric in s0 and s2.
+// in the vacant cells: kVacFirst for window 0 of pairs of 64 columns or more
+// (only the read positions before 0 are vacant: the low -d bits of diagonal
+// d < 0, a constant), kVacAny from the per-lane vacancy words (short pairs and
+// the last windows).  CONT folds in the dead-diagonal bit of a snake that
+// entered inside a pipe (bit 0 of the window).  v_bitop3 takes s1 | (s0 ^ s2)
+// (truth table 0xDE) and its complement (0x21) in one instruction; both are
+// symmetric in s0 and s2.
+constexpr int kVacNone = 0, kVacFirst = 1, kVacAny = 2;
 __device__ __forceinline__ uint32_t or_xor3(uint32_t a, uint32_t t, uint32_t b) {
     return __builtin_amdgcn_bitop3_b32(a, t, b, 0xDE);
 }
@@ -168,7 +172,7 @@ __device__ __forceinline__ uint32_t nor_xor3(uint32_t a, uint32_t t, uint32_t b)
     return __builtin_amdgcn_bitop3_b32(a, t, b, 0x21);
 }
 
-template <int EMAX, bool VAC, bool CONT, typename DT, int I = 0>
+template <int EMAX, int VAC, bool CONT, typename DT, int I = 0>
 __device__ __forceinline__ void chunk_map(const WindowWords& q, DT dead, uint32_t* M) {
     if constexpr (I < 2 * EMAX + 1) {
         constexpr int d = I - EMAX;
@@ -184,9 +188,12 @@ __device__ __forceinline__ void chunk_map(const WindowWords& q, DT dead, uint32_
             hi = funnel(q.chi, q.phi, 32 + d);
         }
         uint32_t t;
-        if constexpr (VAC || CONT) {
+        if constexpr (VAC == kVacFirst && !CONT && d < 0) {
+            t = or_xor3(lo, (1u << -d) - 1u, q.flo);
+        } else if constexpr (VAC == kVacAny || CONT) {
             uint32_t v = 0;
-            if constexpr (VAC) v = diag_vacant<d>(q);
+            if constexpr (VAC == kVacAny) v = diag_vacant<d>(q);
+            if constexpr (VAC == kVacFirst && d < 0) v = (1u << -d) - 1u;
             if constexpr (CONT) v |= (uint32_t)((dead >> I) & 1u);
             t = or_xor3(lo, v, q.flo);
         } else {
@@ -339,18 +346,22 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
             bool cont = t.cont;
             for (uint32_t wk = w; wk < w + span && wave_any(act); ++wk) {
                 const WindowWords q = window_words_direct(P.reads + off, P.refs + off, (int)wk, W, (int)m);
-                // Vacant cells only occur in the first window and near the end.
-                // A snake that entered inside a pipe sees the diagonals whose
-                // pipes ended before this window blocked in its first column.
-                const bool vac = wave_any(act && (wk == 0 || 32u * (wk + 2) > m));
+                // Vacant cells only occur in the first window and near the
+                // pair's end.  A snake that entered inside a pipe sees the
+                // diagonals whose pipes ended before this window blocked in
+                // its first column.
+                const bool near_end = wave_any(act && 32u * (wk + 2) > m);
                 const bool cnt = wave_any(act && cont);
                 uint32_t M[D];
-                if (vac) {
-                    if (cnt) chunk_map<EMAX, true, true>(q, dead, M);
-                    else chunk_map<EMAX, true, false>(q, dead, M);
+                if (near_end) {
+                    if (cnt) chunk_map<EMAX, kVacAny, true>(q, dead, M);
+                    else chunk_map<EMAX, kVacAny, false>(q, dead, M);
+                } else if (wk == 0) {
+                    // No snake is inside a pipe at column 0.
+                    chunk_map<EMAX, kVacFirst, false>(q, dead, M);
                 } else {
-                    if (cnt) chunk_map<EMAX, false, true>(q, dead, M);
-                    else chunk_map<EMAX, false, false>(q, dead, M);
+                    if (cnt) chunk_map<EMAX, kVacNone, true>(q, dead, M);
+                    else chunk_map<EMAX, kVacNone, false>(q, dead, M);
                 }
                 if (mask_E) {
 #pragma unroll
