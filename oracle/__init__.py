@@ -1,9 +1,9 @@
 """CPU oracle -- TEST INFRASTRUCTURE ONLY.
 
 Plain, slow, obviously-correct implementations of what the GPU path computes
-(SneakySnake on the unweighted and weighted maze, GateKeeper, Shouji, banded
-and full Levenshtein distance, the cost-model features, and the cost-model MLP
-in float64).  Only the tests, the package's smoke check and the benchmark's CPU
+(SneakySnake on the unweighted and weighted maze and on a column-partitioned
+maze, GateKeeper, Shouji, banded and full Levenshtein distance, the cost-model
+features, and the cost-model MLP in float64).  Only the tests, the package's smoke check and the benchmark's CPU
 baseline leg may import this package; the product path never does.  It shares
 no code with the GPU library: the C part (oracle.c) is compiled by gcc into its
 own shared object, and the MLP reference (mlp.py) is numpy.
@@ -45,6 +45,9 @@ def _load():
         P, I = ctypes.c_void_p, ctypes.c_int
         lib.or_sneakysnake.argtypes = [P, P, I, I, P, P, I, P]
         lib.or_sneakysnake_weighted.argtypes = [P, P, I, I, P]
+        lib.or_sneakysnake_t.argtypes = [P, P, I, I, I, P]
+        lib.or_sneakysnake_t_batch.argtypes = [P, P, ctypes.c_uint32, P, P, ctypes.c_uint64, I, P, P, I]
+        lib.or_sneakysnake_t_batch.restype = None
         lib.or_gatekeeper.argtypes = [P, P, I, I, P]
         lib.or_shouji.argtypes = [P, P, I, I, P, P]
         lib.or_banded_levenshtein.argtypes = [P, P, I, I]
@@ -94,6 +97,15 @@ def sneakysnake_weighted(read, ref, E):
     rd, rf = _u8(read), _u8(ref)
     cnt = ctypes.c_int(0)
     acc = lib.or_sneakysnake_weighted(_p(rd), _p(rf), rd.shape[0], E, ctypes.byref(cnt))
+    return bool(acc), cnt.value
+
+
+def sneakysnake_t(read, ref, E, t):
+    """(accept, count) of SneakySnake on the maze cut into sub-mazes of t columns."""
+    lib = _load()
+    rd, rf = _u8(read), _u8(ref)
+    cnt = ctypes.c_int(0)
+    acc = lib.or_sneakysnake_t(_p(rd), _p(rf), rd.shape[0], E, t, ctypes.byref(cnt))
     return bool(acc), cnt.value
 
 
@@ -177,6 +189,20 @@ def filter_batch(reads, refs, lens, Es, filters=SNEAKYSNAKE, threads=None):
     lib.or_filter_batch(_p(reads), _p(refs), stride, _p(lens), _p(Es), n, filters, *bufs,
                         _threads(threads))
     return out
+
+
+def sneakysnake_t_batch(reads, refs, lens, Es, t, threads=None):
+    """(accept uint8[n], count uint16[n]) of SneakySnake-t over a batch."""
+    lib = _load()
+    reads, refs = _u8(reads), _u8(refs)
+    n, stride = reads.shape
+    lens = np.ascontiguousarray(np.asarray(lens, np.uint16))
+    Es = np.ascontiguousarray(np.broadcast_to(np.asarray(Es, np.uint8), (n,)))
+    a = np.zeros(n, np.uint8)
+    c = np.zeros(n, np.uint16)
+    lib.or_sneakysnake_t_batch(_p(reads), _p(refs), stride, _p(lens), _p(Es), n, int(t), _p(a), _p(c),
+                               _threads(threads))
+    return a, c
 
 
 def banded_batch(reads, refs, lens, Es, threads=None) -> np.ndarray:

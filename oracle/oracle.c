@@ -91,6 +91,41 @@ int or_sneakysnake(const uint8_t* read, const uint8_t* ref, int m, int E, int* c
     return e <= E;
 }
 
+/* SneakySnake on a column-partitioned maze (Sec. 8.6, the hardware design's
+ * sub-matrices; its software form with t = 5, 10, 25 or 50 columns is the
+ * SneakySnake-t of Sec. 9.3.1).  The maze is cut into adjacent,
+ * non-overlapping sub-mazes of t columns each (the last one narrower when t
+ * does not divide m), all 2E+1 diagonals high, and each sub-maze is solved on
+ * its own by the same greedy: a pipe is probed only up to the sub-maze's last
+ * column, reaching that column costs nothing, and the snake enters the next
+ * sub-maze free to take any diagonal.  The obstacles crossed in all sub-mazes
+ * add up; the search stops once the sum exceeds E.  With t >= m there is one
+ * sub-maze, the whole maze.
+ * Returns accept (0/1); *count = min(total obstacles, E + 1). */
+int or_sneakysnake_t(const uint8_t* read, const uint8_t* ref, int m, int E, int t, int* count) {
+    int e = 0;
+    for (int p0 = 0; p0 < m && e <= E; p0 += t) {
+        int p1 = p0 + t < m ? p0 + t : m;         /* this sub-maze: columns [p0, p1) */
+        int c = p0;
+        while (c < p1) {
+            int best = 0;
+            for (int d = -E; d <= E; ++d) {
+                int L = 0;
+                while (c + L < p1 && map_cell(read, ref, m, c + L, d, 1) == 0) L++;
+                if (L > best) best = L;
+            }
+            c += best;
+            if (c < p1) {                         /* an obstacle inside the sub-maze */
+                e += 1;
+                c += 1;
+                if (e > E) break;
+            }
+        }
+    }
+    *count = e;
+    return e <= E;
+}
+
 /* SneakySnake on the weighted maze (Sec. 8.3, Eq. 8.1): each available cell holds the
  * number of available cells from it to the end of its pipe, filled from the
  * lower right; the snake reads the largest weight in its column instead of
@@ -303,6 +338,20 @@ void or_filter_batch(const uint8_t* reads, const uint8_t* refs, uint32_t stride,
             acc_sh[i] = (uint8_t)or_shouji(rd, rf, m, e, &cnt, NULL);
             cnt_sh[i] = (uint16_t)cnt;
         }
+    }
+}
+
+/* SneakySnake-t over a batch (pairs as in or_filter_batch). */
+void or_sneakysnake_t_batch(const uint8_t* reads, const uint8_t* refs, uint32_t stride,
+                            const uint16_t* len, const uint8_t* E, uint64_t n, int t,
+                            uint8_t* acc, uint16_t* cnt, int nthreads) {
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 256)
+    for (int64_t i = 0; i < (int64_t)n; ++i) {
+        int c = 0;
+        acc[i] = (uint8_t)or_sneakysnake_t(reads + (uint64_t)i * stride, refs + (uint64_t)i * stride,
+                                           len[i], E[i], t, &c);
+        cnt[i] = (uint16_t)c;
     }
 }
 

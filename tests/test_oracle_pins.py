@@ -332,3 +332,109 @@ def test_features_closed_form():
     y = x.copy()
     y[70:] = (y[70:] + 1) % 4
     assert oracle.features(x, y, 5)[32] == 1.0
+
+
+# ---------------------------------------------------------------- SneakySnake-t
+def _maze(read, ref, E):
+    """Blocked (1) / free (0) cells of the unweighted maze, rows d = -E..E,
+    built with numpy straight from the cell definition."""
+    m = len(ref)
+    read, ref = np.asarray(read), np.asarray(ref)
+    Z = np.ones((2 * E + 1, m), np.uint8)
+    for k, d in enumerate(range(-E, E + 1)):
+        for c in range(m):
+            if 0 <= c + d < m:
+                Z[k, c] = int(read[c + d] != ref[c])
+    return Z
+
+
+def _least_obstacles(Z, p0, p1):
+    """Fewest obstacles a snake crosses from column p0 to the end of the
+    sub-maze [p0, p1), by dynamic programming over every choice of pipe (no
+    greedy rule): from a free column it may follow any row to its first
+    obstacle (or to the sub-maze's end, at no cost) and cross that obstacle
+    for one."""
+    f = [0] * (p1 - p0 + 2)
+    for c in range(p1 - 1, p0 - 1, -1):
+        best = None
+        for row in Z:
+            r = 0
+            while c + r < p1 and row[c + r] == 0:
+                r += 1
+            cost = 0 if c + r == p1 else 1 + f[c + r + 1 - p0]
+            best = cost if best is None else min(best, cost)
+        f[c - p0] = best
+    return f[0]
+
+
+def test_sneakysnake_t_greedy_takes_least_obstacles():
+    # Sec. 8.6: within each sub-maze the greedy finds the path with the fewest
+    # obstacles; the partitioned count is the sum over sub-mazes.
+    rng = np.random.default_rng(11)
+    for _ in range(600):
+        m = int(rng.integers(1, 25))
+        E = int(rng.integers(0, 5))
+        a = rng.integers(0, 4, m).astype(np.uint8)
+        b = a.copy()
+        for _ in range(int(rng.integers(0, 6))):
+            b[int(rng.integers(0, m))] = rng.integers(0, 4)
+        if rng.random() < 0.5 and m > 2:
+            i = int(rng.integers(0, m))
+            b = np.concatenate([b[:i], b[i + 1:], rng.integers(0, 4, 1)]).astype(np.uint8)
+        Z = _maze(a, b, E)
+        for t in (1, 2, 3, 5, 7, m, m + 3):
+            total = sum(_least_obstacles(Z, p0, min(p0 + t, m)) for p0 in range(0, m, t))
+            acc, cnt = oracle.sneakysnake_t(a, b, E, t)
+            assert cnt == min(total, E + 1), (m, E, t)
+            assert acc == (total <= E)
+        # One sub-maze is the whole maze.
+        assert oracle.sneakysnake(a, b, E)[1] == min(_least_obstacles(Z, 0, m), E + 1)
+
+
+def test_sneakysnake_t_single_columns_count_blocked_columns():
+    # t = 1: every column is its own sub-maze, which costs one exactly when all
+    # of its 2E+1 cells are blocked.
+    p = pairgen.generate(pairgen.SMALL_100BP, 0, 300)
+    for i in range(p.n):
+        for E in (0, 1, 3):
+            blocked = int(_maze(p.reads[i], p.refs[i], E).min(0).sum())
+            assert oracle.sneakysnake_t(p.reads[i], p.refs[i], E, 1) == (blocked <= E, min(blocked, E + 1))
+
+
+def test_sneakysnake_t_wide_partition_is_whole_maze():
+    p = pairgen.generate(pairgen.FIXED_250BP, 0, 500)
+    for E in (0, 5, 10):
+        whole = oracle.filter_batch(p.reads, p.refs, p.len, E)[1]
+        for t in (250, 251, 512):
+            a, c = oracle.sneakysnake_t_batch(p.reads, p.refs, p.len, E, t)
+            assert np.array_equal(a, whole[0]) and np.array_equal(c, whole[1])
+
+
+def test_sneakysnake_t_nested_partitions_and_zero_false_rejects():
+    # A partition that refines another can only lose obstacles (each sub-maze
+    # path restricted to a finer sub-maze is a path there), so t | t' gives
+    # count_t <= count_t' <= the whole maze's count <= the banded distance.
+    p = pairgen.generate(pairgen.FIXED_250BP, 1, 2000)
+    E = 10
+    whole = oracle.filter_batch(p.reads, p.refs, p.len, E)[1][1].astype(int)
+    band = oracle.banded_batch(p.reads, p.refs, p.len, E).astype(int)
+    c = {t: oracle.sneakysnake_t_batch(p.reads, p.refs, p.len, E, t)[1].astype(int) for t in (5, 10, 25, 50)}
+    assert np.all(c[5] <= c[10]) and np.all(c[10] <= c[50]) and np.all(c[25] <= c[50])
+    assert np.all(c[50] <= whole) and np.all(whole <= band)
+    # ... and on tiny inputs exhaustively, for every partition width.
+    reads, refs = _all_pairs(4)
+    n = reads.shape[0]
+    for E in range(0, 3):
+        band = oracle.banded_batch(reads, refs, np.full(n, 4), np.full(n, E)).astype(int)
+        for t in (1, 2, 3):
+            a, cnt = oracle.sneakysnake_t_batch(reads, refs, np.full(n, 4), np.full(n, E), t)
+            assert np.all(cnt.astype(int) <= band) and np.all(a[band <= E] == 1)
+
+
+def test_sneakysnake_t_E0_is_hamming_capped():
+    # One diagonal: every mismatch is an obstacle of its sub-maze.
+    p = pairgen.generate(pairgen.SMALL_100BP, 0, 2000)
+    ham = (p.reads != p.refs).sum(1)
+    for t in (1, 5, 10, 100):
+        a, c = oracle.sneakysnake_t_batch(p.reads, p.refs, p.len, 0, t)
+        assert np.array_equal(c, np.minimum(ham, 1)) and np.array_equal(a, (ham == 0).astype(np.uint8))
