@@ -129,6 +129,23 @@ paf_status paf_pack_host(const uint8_t* codes, uint32_t code_stride, const uint1
 paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, const paf_out* out,
                       void* stream);
 
+/* SneakySnake on a column-partitioned maze (Sec. 8.6: the maze is cut into
+ * adjacent, non-overlapping sub-mazes of t columns, all 2E+1 diagonals high,
+ * the last one narrower when t does not divide m; Sec. 9.3.1 evaluates the
+ * software form, SneakySnake-t, at t = 5, 10, 25 and 50).  Each sub-maze is
+ * solved on its own by the greedy of paf_filter: a pipe is probed only up to
+ * the sub-maze's last column, reaching that column costs nothing, and the
+ * snake enters the next sub-maze free to take any diagonal.  The obstacles of
+ * all sub-mazes add up: count = min(sum, E+1), accept = sum <= E.  The count
+ * never exceeds the whole maze's (so there are no false rejects either), and
+ * t >= m gives paf_filter's SneakySnake result.  t in [1, PAF_MAX_PART].
+ * Writes out->accept_bits[0] and out->count[0] (the SneakySnake slots; the
+ * others are ignored).  Runs on the compacting engine with paf_filter's
+ * layout (a forced layout applies when its chunk_tiles > 0). */
+#define PAF_MAX_PART 65535
+paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t t, const paf_out* out,
+                                  void* stream);
+
 /* Persistent launch: the same filter as one launch over 64-pair tiles, or
  * over compacting chunks of tiles for SneakySnake alone, handed out by a work
  * queue (the Read Controller's role, Sec. 4.2.1) or by the hardware

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libpaf.so")
 SNEAKYSNAKE, GATEKEEPER, SHOUJI = 1, 2, 4
 ALL_FILTERS = SNEAKYSNAKE | GATEKEEPER | SHOUJI
 MAX_LEN, MAX_E = 512, 31
+MAX_PART = 65535  # widest sub-maze of paf_filter_partitioned
 MLP_NPARAMS = 24961
 
 STATUS = {0: "PAF_OK", 1: "PAF_ERR_ARG", 2: "PAF_ERR_RANGE", 3: "PAF_ERR_DEVICE",
@@ -27,7 +28,7 @@ STATUS = {0: "PAF_OK", 1: "PAF_ERR_ARG", 2: "PAF_ERR_RANGE", 3: "PAF_ERR_DEVICE"
 
 # Every symbol declared in include/paf.h.
 EXPORTS = ("paf_create", "paf_destroy", "paf_last_error", "paf_check", "paf_pack", "paf_pack_host",
-           "paf_filter", "paf_filter_persistent", "paf_autotune", "paf_set_layout", "paf_features",
+           "paf_filter", "paf_filter_partitioned", "paf_filter_persistent", "paf_autotune", "paf_set_layout", "paf_features",
            "paf_mlp_set_params", "paf_mlp_get_params", "paf_mlp_forward", "paf_mlp_train_step",
            "paf_mlp_predict", "paf_mlp_train", "paf_bucket", "paf_filter_ordered", "paf_filter_bucketed",
            "paf_filter_bucketed_local", "paf_cost_levels", "paf_filter_keyed", "paf_stream_filter")
@@ -93,6 +94,7 @@ def load_library(path: str = LIB_PATH):
         "paf_pack_host": ([P, U32, P, ctypes.c_uint16, P, U32, U64, P, I]),
         "paf_filter": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
         "paf_filter_persistent": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
+        "paf_filter_partitioned": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
         "paf_autotune": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P,
                           ctypes.POINTER(Layout), ctypes.POINTER(ctypes.c_float),
                           ctypes.POINTER(ctypes.c_float)]),
@@ -260,6 +262,13 @@ class Context:
         out = out or self.alloc_out(batch.n_pairs, filters, batch.device)
         cb, co = batch.c(), self._out(out)
         _check(self.lib.paf_filter(self.h, ctypes.byref(cb), filters, ctypes.byref(co), _stream(stream)))
+        return out
+
+    def filter_partitioned(self, batch: Batch, t: int, out: dict | None = None, stream=None) -> dict:
+        """SneakySnake on the maze cut into sub-mazes of t columns."""
+        out = out or self.alloc_out(batch.n_pairs, SNEAKYSNAKE, batch.device)
+        cb, co = batch.c(), self._out(out)
+        _check(self.lib.paf_filter_partitioned(self.h, ctypes.byref(cb), t, ctypes.byref(co), _stream(stream)))
         return out
 
     def filter_persistent(self, batch: Batch, filters: int = SNEAKYSNAKE, out: dict | None = None,

@@ -427,6 +427,38 @@ paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, co
     return PAF_OK;
 }
 
+paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t t, const paf_out* out,
+                                 void* stream) {
+    const uint32_t filters = PAF_SNEAKYSNAKE;
+    FilterParams p;
+    paf_status st = check_batch(ctx, batch, filters, p);
+    if (st != PAF_OK) return st;
+    if ((st = check_out(out, filters)) != PAF_OK) return st;
+    if (t < 1 || t > PAF_MAX_PART) return fail(PAF_ERR_RANGE, "partition width outside [1, PAF_MAX_PART]");
+    const int emax = emax_bucket((int)p.max_E);
+    if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
+    set_outputs(p, out);
+    p.part = t;
+    const bool general = batch->len || batch->E || batch->word_offset;
+    // The compacting engine, as a full grid of chunks (a forced layout that
+    // compacts sets the chunk size, block shape and pass widths).
+    const paf_layout PL = ctx->layout_forced && ctx->forced.chunk_tiles > 0 ? ctx->forced : plain_layout();
+    p.chunk = PL.chunk_tiles;
+    p.span0 = std::max(1u, PL.first_pass_windows);
+    p.span = std::max(1u, PL.pass_windows);
+    LaunchShape sh;
+    sh.waves_per_block = PL.waves_per_block;
+    sh.lds_bytes = chunk_lds_bytes(sh.waves_per_block, general, emax, p.chunk);
+    if (sh.lds_bytes > 160 * 1024) return fail(PAF_ERR_RANGE, "layout needs more LDS than a CU has");
+    const uint64_t units = (p.n_tiles + p.chunk - 1) / p.chunk;
+    sh.blocks = (uint32_t)((units + sh.waves_per_block - 1) / sh.waves_per_block);
+    PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    PAF_HIP(allow_lds(filter_kernel_ptr(Engine::ChunkPart, general, emax, p.filters), sh.lds_bytes),
+            "hipFuncSetAttribute");
+    PAF_HIP(launch_filter(p, Engine::ChunkPart, general, emax, sh, (hipStream_t)stream), "filter launch");
+    return PAF_OK;
+}
+
 paf_status paf_filter_persistent(paf_ctx* ctx, const paf_batch* batch, uint32_t filters,
                                  const paf_out* out, void* stream) {
     FilterParams p;

@@ -213,7 +213,11 @@ struct ChunkLds {
     uint32_t* acc;   // 2 K accept words (plain order)
 };
 
-template <int EMAX, bool GENERAL>
+// PART: the maze is cut into sub-mazes of P.part columns, each solved on its
+// own (Sec. 8.6; SneakySnake-t of Sec. 9.3.1).  A lane then also tracks pe,
+// the first column of the next sub-maze: a probe's run is cut at pe, reaching
+// pe costs nothing, and the snake leaves pe free to take any diagonal.
+template <int EMAX, bool GENERAL, bool PART>
 __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, int lane,
                             const ChunkLds<EMAX, GENERAL>& L) {
     constexpr int D = 2 * EMAX + 1;
@@ -344,6 +348,10 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
             const int W = (int)((m + 31) >> 5);
             uint32_t c = t.c, e = t.e;
             bool cont = t.cont;
+            // A snake inside a pipe at a window's start is never at a
+            // sub-maze's first column (reaching that column ends the pipe), so
+            // pe follows from c alone.
+            uint32_t pe = PART ? (c / P.part + 1u) * P.part : 0u;
             for (uint32_t wk = w; wk < w + span && wave_any(act); ++wk) {
                 const WindowWords q = window_words_direct(P.reads + off, P.refs + off, (int)wk, W, (int)m);
                 // Vacant cells only occur in the first window and near the
@@ -392,16 +400,31 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                         r0 = or_andn(r0, M[d], M[d] + bs);
                         if (d + 1 < D) r1 = or_andn(r1, M[d + 1], M[d + 1] + bs);
                     }
-                    const uint32_t runs = r0 | r1;
-                    clear = runs >> 31;
-                    // The obstacle's column; when a pipe runs past the window
-                    // the run is [s, 32) and this is the window's end.
-                    const uint32_t R = c + (uint32_t)__builtin_popcount(runs);
-                    // An obstacle inside the pair (R < m) counts one edit.
-                    e += ((R - m) >> 31) & (clear ^ 1u);
-                    // Cross the obstacle (R + 1), or stay at the window's end
-                    // inside the pipe (R).
-                    c = R + 1u - clear;
+                    uint32_t runs = r0 | r1;
+                    if constexpr (PART) {
+                        // The run stops at the sub-maze's end pe; reaching
+                        // it is free (at), and so is the window's end when
+                        // pe lies beyond it (clear: the pipe goes on).
+                        const uint32_t cut = pe - w0;
+                        runs &= cut < 32u ? (1u << cut) - 1u : ~0u;
+                        const uint32_t R = c + (uint32_t)__builtin_popcount(runs);
+                        const uint32_t at = R == pe ? 1u : 0u;
+                        clear = (runs >> 31) & (at ^ 1u);
+                        e += ((R - m) >> 31) & ((clear | at) ^ 1u);
+                        c = R + 1u - clear - at;
+                        pe += c == pe ? P.part : 0u;
+                    } else {
+                        clear = runs >> 31;
+                        // The obstacle's column; when a pipe runs past the
+                        // window the run is [s, 32) and this is the window's
+                        // end.
+                        const uint32_t R = c + (uint32_t)__builtin_popcount(runs);
+                        // An obstacle inside the pair (R < m) counts one edit.
+                        e += ((R - m) >> 31) & (clear ^ 1u);
+                        // Cross the obstacle (R + 1), or stay at the window's
+                        // end inside the pipe (R).
+                        c = R + 1u - clear;
+                    }
                 }
                 // A lane is decided once it crossed the pair's end (accept
                 // exactly when e <= E) or counted E + 1 edits.
@@ -467,7 +490,7 @@ __host__ __device__ constexpr size_t chunk_wave_bytes_t(uint32_t K) {
     return (size_t)K * 64 * (8 + sizeof(DT) + (GENERAL ? 8 : 0)) + (size_t)K * 8;
 }
 
-template <int EMAX, bool GENERAL>
+template <int EMAX, bool GENERAL, bool PART>
 __global__ void __launch_bounds__(512) chunk_kernel(FilterParams P) {
     extern __shared__ uint64_t lds[];
     using DT = typename DeadMask<EMAX>::T;
@@ -491,7 +514,7 @@ __global__ void __launch_bounds__(512) chunk_kernel(FilterParams P) {
     const uint32_t n_chunks = (P.n_tiles + K - 1) / K;
     if (P.queue == nullptr) {
         const uint32_t ch = blockIdx.x * (blockDim.x >> 6) + wave;
-        if (ch < n_chunks) chunk_snake<EMAX, GENERAL>(P, ch, K, lane, L);
+        if (ch < n_chunks) chunk_snake<EMAX, GENERAL, PART>(P, ch, K, lane, L);
         return;
     }
     uint32_t c0 = 0;
@@ -500,17 +523,17 @@ __global__ void __launch_bounds__(512) chunk_kernel(FilterParams P) {
     while (c0 < n_chunks) {
         uint32_t nx = 0;
         if (lane == 0) nx = atomicAdd(P.queue, 1u);
-        chunk_snake<EMAX, GENERAL>(P, c0, K, lane, L);
+        chunk_snake<EMAX, GENERAL, PART>(P, c0, K, lane, L);
         wave_lds_sync();
         c0 = __shfl(nx, 0);
     }
 }
 
-template <bool GENERAL>
+template <bool GENERAL, bool PART>
 const void* chunk_kernel_for(int emax) {
     switch (emax) {
 #define PAF_CASE(X) \
-    case X: return reinterpret_cast<const void*>(&chunk_kernel<X, GENERAL>);
+    case X: return reinterpret_cast<const void*>(&chunk_kernel<X, GENERAL, PART>);
         PAF_CASE(0) PAF_CASE(1) PAF_CASE(2) PAF_CASE(3) PAF_CASE(4) PAF_CASE(5) PAF_CASE(6)
         PAF_CASE(7) PAF_CASE(8) PAF_CASE(10) PAF_CASE(12) PAF_CASE(15) PAF_CASE(20) PAF_CASE(25)
         PAF_CASE(31)
@@ -610,7 +633,9 @@ int emax_bucket(int max_E) {
 }
 
 const void* filter_kernel_ptr(Engine eng, bool general, int emax, uint32_t filters) {
-    if (eng == Engine::Chunk) return general ? chunk_kernel_for<true>(emax) : chunk_kernel_for<false>(emax);
+    if (eng == Engine::Chunk) return general ? chunk_kernel_for<true, false>(emax) : chunk_kernel_for<false, false>(emax);
+    if (eng == Engine::ChunkPart)
+        return general ? chunk_kernel_for<true, true>(emax) : chunk_kernel_for<false, true>(emax);
     if (eng == Engine::Snake) return general ? snake_kernel_for<true>(emax) : snake_kernel_for<false>(emax);
     return whole_kernel_ptr(general, emax, filters);
 }

@@ -42,10 +42,11 @@ struct FilterParams {
     uint32_t span0, span;   // compacting engine: windows of the first pass and of later passes
     const uint8_t* order_key;  // compacting engine: per-pair key (original order); each chunk's
                                // pairs enter the first window in ascending key order, or NULL
+    uint32_t part;             // compacting engine, partitioned maze: sub-maze width in columns
 };
 
 // Kernel selection.
-enum class Engine { Snake, Whole, Chunk };
+enum class Engine { Snake, Whole, Chunk, ChunkPart };
 
 struct LaunchShape {
     uint32_t waves_per_block;
