@@ -147,12 +147,15 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="time the plain filter only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="fixed250",
-                    choices=["fixed250", "filters", "uneven", "learned-uneven", "stream"],
+                    choices=["fixed250", "filters", "partitioned", "verify", "uneven", "learned-uneven", "stream"],
                     help="fixed250 (default): 10M x 250 bp at E (plain and learned-bucketed); filters: the "
                          "same pairs at E = 0, 5, 10, 25 with SneakySnake, GateKeeper, Shouji and all three "
                          "on one map; uneven: 50M pairs of mixed lengths in the persistent launch, default "
                          "vs autotuned layout; learned-uneven: the same batch, learned-bucketed vs plain; "
-                         "stream: 200M pairs streamed from pinned host memory in 8M-pair chunks")
+                         "stream: 200M pairs streamed from pinned host memory in 8M-pair chunks; "
+                         "partitioned: SneakySnake on sub-mazes of t = 5, 10, 25, 50 columns vs the whole maze "
+                         "at E = 0, 5, 10, 25; verify: banded edit distance of the pairs SneakySnake accepts "
+                         "(filter + verify) vs verifying every pair, at E = 5, 10, 25")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain copy kernel of known size (counter calibration)")
     args = ap.parse_args()
@@ -175,6 +178,9 @@ def main():
 
     if args.workload == "filters":
         filters_workload(args)
+        return
+    if args.workload in ("partitioned", "verify"):
+        next_workloads(args)
         return
     if args.workload != "fixed250":
         other_workload(args)
@@ -466,6 +472,85 @@ def other_workload(args):
           "plain": {"value": n / res[False][1]["seconds"], "seconds": res[False][1]["seconds"],
                     "h2d_GBps": res[False][1]["h2d_bytes"] / res[False][1]["seconds"] / 1e9},
           "identical_decisions": same})
+
+
+def next_workloads(args):
+    """10M x 250 bp pairs: SneakySnake on partitioned mazes (sub-mazes of t
+    columns), or the filter followed by verification of its survivors."""
+    import dataclasses
+
+    import torch
+
+    import pairgen
+    import paper_1910_03936_amd as paf
+
+    ctx = paf.Context(0)
+    dev = torch.device("cuda", 0)
+    w = pairgen.FIXED_250BP
+    n = args.pairs or w.n_pairs
+    base, _ = build_batch(ctx, w, n, dev)
+    W = paf.words_for(250)
+    SS = paf.SNEAKYSNAKE
+    steps = max(3, args.steps // 2)
+    out = ctx.alloc_out(n, SS, dev)
+    t = time.perf_counter()
+    while time.perf_counter() - t < 0.3:
+        ctx.filter(base, SS, out=out)
+        torch.cuda.synchronize()
+
+    def timed(fn):
+        per, _, _ = time_steps(fn, steps, args.warmup)
+        ctx.check()
+        return sum(per) / len(per)
+
+    if args.workload == "partitioned":
+        by_E = {}
+        for E in (0, 5, 10, 25):
+            b = dataclasses.replace(base, uniform_E=E, max_E=E)
+            row = {"whole maze": {"ms": round(timed(lambda: ctx.filter(b, SS, out=out)), 4)}}
+            row["whole maze"]["accept_rate"] = float(paf.accept_bits_to_bool(out[SS][0], n).float().mean())
+            for tp in (5, 10, 25, 50):
+                ms = timed(lambda: ctx.filter_partitioned(b, tp, out=out))
+                acc = float(paf.accept_bits_to_bool(out[SS][0], n).float().mean())
+                row[f"t={tp}"] = {"ms": round(ms, 4), "accept_rate": round(acc, 5)}
+            by_E[str(E)] = row
+            log(f"E={E}: " + ", ".join(f"{k} {v['ms']:.3f} ms (acc {v['accept_rate']:.4f})" for k, v in row.items()))
+        r = by_E["10"]["t=5"]
+        gbs = n * (2 * W * 8 + 2 + 1 / 8) / (r["ms"] / 1e3) / 1e9
+        emit(args, n / (r["ms"] / 1e3), r["ms"],
+             f"{n} pairs, 250 bp, 2-bit packed, 70% unrelated, k~U{{0..40}}; SneakySnake on sub-mazes of t "
+             f"columns (compacting engine); value at E=10, t=5",
+             {"pairs": n, "read_len": 250, "E": [0, 5, 10, 25], "t": [5, 10, 25, 50]},
+             {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+              "kernel": "chunk_kernel<E=10, uniform, partitioned>", "kernel_ms": r["ms"],
+              "alg_bytes_per_pair": round(2 * W * 8 + 2 + 1 / 8, 3)},
+             None, {"by_E": by_E})
+        ctx.close()
+        return
+    by_E = {}
+    for E in (5, 10, 25):
+        b = dataclasses.replace(base, uniform_E=E, max_E=E)
+        dist = torch.empty(n, dtype=torch.int16, device=dev)
+        filt_ms = timed(lambda: ctx.filter(b, SS, out=out))
+        surv = int(paf.accept_bits_to_bool(out[SS][0], n).sum())
+        ver_ms = timed(lambda: ctx.verify(b, out[SS][0], dist=dist))
+        d_sel = dist.clone()
+        all_ms = timed(lambda: ctx.verify(b, dist=dist))
+        same = bool(torch.equal(d_sel, dist))
+        within = int((paf.counts_u16(dist) <= E).sum())
+        by_E[str(E)] = {"filter_ms": round(filt_ms, 4), "survivors": surv,
+                        "verify_survivors_ms": round(ver_ms, 4), "filter_plus_verify_ms": round(filt_ms + ver_ms, 4),
+                        "verify_every_pair_ms": round(all_ms, 4), "identical_distances": same,
+                        "pairs_within_E": within}
+        log(f"E={E}: filter {filt_ms:.3f} ms, {surv} survivors verified in {ver_ms:.3f} ms; every pair "
+            f"{all_ms:.3f} ms; identical {same}; {within} pairs within E")
+    r = by_E["10"]
+    emit(args, n / (r["filter_plus_verify_ms"] / 1e3), r["filter_plus_verify_ms"],
+         f"{n} pairs, 250 bp, 2-bit packed, 70% unrelated, k~U{{0..40}}; SneakySnake, then banded edit distance "
+         f"of its survivors; value at E=10",
+         {"pairs": n, "read_len": 250, "E": [5, 10, 25]}, None, None, {"by_E": by_E})
+    ctx.close()
 
 
 if __name__ == "__main__":

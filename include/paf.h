@@ -146,6 +146,25 @@ paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, co
 paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t t, const paf_out* out,
                                   void* stream);
 
+/* Verification of filtered pairs: dist[p] = min(edit distance, E+1) of the
+ * pair's reference segment and read, over alignments that stay inside the
+ * band of the 2E+1 diagonals the filter examined (Ukkonen's banded edit
+ * distance; Sec. 8.7 restricts exact edit distance to the cells that are
+ * needed, and Sec. 9.3.1 pairs SneakySnake with such an aligner).  A value
+ * <= E is the pair's exact edit distance; E+1 means more than E edits.
+ * select_bits [device, ceil(n/32) words] or NULL: only the pairs whose bit is
+ * set (bit p % 32 of word p / 32, the layout of paf_out's accept bits) are
+ * verified, the others get E+1 (they were rejected); NULL verifies every
+ * pair.  Passing SneakySnake's accept bits gives exactly the result of
+ * verifying every pair, since SneakySnake never rejects a pair within E
+ * edits.  dist [device]: n_pairs uint16, at the original pair index.  Work
+ * grows with each pair's distance (by diagonal transition, E+1 rounds at
+ * most); each wave gathers the selected pairs of 1024 consecutive ones into
+ * full groups of 64, so only the selected pairs cost time.  Needs no
+ * workspace. */
+paf_status paf_verify(paf_ctx* ctx, const paf_batch* batch, const uint32_t* select_bits, uint16_t* dist,
+                      void* stream);
+
 /* Persistent launch: the same filter as one launch over 64-pair tiles, or
  * over compacting chunks of tiles for SneakySnake alone, handed out by a work
  * queue (the Read Controller's role, Sec. 4.2.1) or by the hardware

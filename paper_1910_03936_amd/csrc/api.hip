@@ -459,6 +459,20 @@ paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t
     return PAF_OK;
 }
 
+paf_status paf_verify(paf_ctx* ctx, const paf_batch* batch, const uint32_t* select_bits, uint16_t* dist,
+                      void* stream) {
+    FilterParams p;
+    paf_status st = check_batch(ctx, batch, PAF_SNEAKYSNAKE, p);
+    if (st != PAF_OK) return st;
+    if (!dist) return fail(PAF_ERR_ARG, "dist is NULL");
+    const int emax = emax_bucket((int)p.max_E);
+    if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
+    PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    PAF_HIP(launch_verify(p, emax, select_bits, dist, (hipStream_t)stream),
+            "verify launch");
+    return PAF_OK;
+}
+
 paf_status paf_filter_persistent(paf_ctx* ctx, const paf_batch* batch, uint32_t filters,
                                  const paf_out* out, void* stream) {
     FilterParams p;

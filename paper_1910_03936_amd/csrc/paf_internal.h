@@ -82,6 +82,10 @@ const void* whole_kernel_ptr(bool general, int emax, uint32_t filters);
 size_t filter_lds_bytes(uint32_t waves_per_block, uint32_t wmax);
 size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_t chunk_tiles);
 
+// verify.hip: banded edit distance of the selected pairs (sel: accept-bit
+// words, or NULL for every pair).
+hipError_t launch_verify(const FilterParams& p, int emax, const uint32_t* sel, uint16_t* dist, hipStream_t s);
+
 // mlp.hip
 struct MlpDev {
     float* master = nullptr;  // PAF_MLP_NPARAMS fp32 master weights (host layout of paf.h)
