@@ -2,9 +2,10 @@
 
 Plain, slow, obviously-correct implementations of what the GPU path computes
 (SneakySnake on the unweighted and weighted maze and on a column-partitioned
-maze, GateKeeper, Shouji, banded and full Levenshtein distance, the cost-model
-features, and the cost-model MLP in float64).  Only the tests, the package's smoke check and the benchmark's CPU
-baseline leg may import this package; the product path never does.  It shares
+maze, GateKeeper, Shouji, MAGNET, banded and full Levenshtein distance, the
+cost-model features, and the cost-model MLP in float64).  Only the tests, the
+package's smoke check and the benchmark's CPU baseline leg may import this
+package; the product path never does.  It shares
 no code with the GPU library: the C part (oracle.c) is compiled by gcc into its
 own shared object, and the MLP reference (mlp.py) is numpy.
 """
@@ -46,6 +47,9 @@ def _load():
         lib.or_sneakysnake.argtypes = [P, P, I, I, P, P, I, P]
         lib.or_sneakysnake_weighted.argtypes = [P, P, I, I, P]
         lib.or_sneakysnake_t.argtypes = [P, P, I, I, I, P]
+        lib.or_magnet.argtypes = [P, P, I, I, P, P, P]
+        lib.or_magnet_batch.argtypes = [P, P, ctypes.c_uint32, P, P, ctypes.c_uint64, P, P, I]
+        lib.or_magnet_batch.restype = None
         lib.or_sneakysnake_t_batch.argtypes = [P, P, ctypes.c_uint32, P, P, ctypes.c_uint64, I, P, P, I]
         lib.or_sneakysnake_t_batch.restype = None
         lib.or_gatekeeper.argtypes = [P, P, I, I, P]
@@ -107,6 +111,32 @@ def sneakysnake_t(read, ref, E, t):
     cnt = ctypes.c_int(0)
     acc = lib.or_sneakysnake_t(_p(rd), _p(rf), rd.shape[0], E, t, ctypes.byref(cnt))
     return bool(acc), cnt.value
+
+
+def magnet(read, ref, E, with_segments=False):
+    """(accept, count[, segments]) of MAGNET; segments = [(diagonal, start, length)] in the order found."""
+    lib = _load()
+    rd, rf = _u8(read), _u8(ref)
+    cnt = ctypes.c_int(0)
+    segs = np.zeros(3 * (E + 1), np.int32)
+    ns = ctypes.c_int(0)
+    acc = lib.or_magnet(_p(rd), _p(rf), rd.shape[0], E, ctypes.byref(cnt), _p(segs), ctypes.byref(ns))
+    if with_segments:
+        return bool(acc), cnt.value, [tuple(int(x) for x in segs[3 * i:3 * i + 3]) for i in range(ns.value)]
+    return bool(acc), cnt.value
+
+
+def magnet_batch(reads, refs, lens, Es, threads=None):
+    """(accept uint8[n], count uint16[n]) of MAGNET over a batch."""
+    lib = _load()
+    reads, refs = _u8(reads), _u8(refs)
+    n, stride = reads.shape
+    lens = np.ascontiguousarray(np.asarray(lens, np.uint16))
+    Es = np.ascontiguousarray(np.broadcast_to(np.asarray(Es, np.uint8), (n,)))
+    a = np.zeros(n, np.uint8)
+    c = np.zeros(n, np.uint16)
+    lib.or_magnet_batch(_p(reads), _p(refs), stride, _p(lens), _p(Es), n, _p(a), _p(c), _threads(threads))
+    return a, c
 
 
 def gatekeeper(read, ref, E):

@@ -239,6 +239,63 @@ int or_shouji(const uint8_t* read, const uint8_t* ref, int m, int E, int* count,
     return n <= E;
 }
 
+/* MAGNET (Ch. 7) on the neighborhood map of Ch. 6 (vacant cells blocked).
+ * Extraction: the longest run of consecutive zeros over all 2E+1 diagonals,
+ * among the columns still in the search space.  Encapsulation: the run's
+ * columns and the one column on each side of it leave the search space of
+ * every diagonal.  The two sides are searched again the same way, longest
+ * run first (the hardware form keeps one problem and sets the excluded
+ * columns to ones in every bit-vector, Sec. 7.4), until E + 1 runs are found
+ * or no zero is left.  The pair is rejected when the runs found cover fewer
+ * than m - E columns.
+ * Readings: among runs of equal length the one with the smallest start
+ * column is taken, then the first diagonal in order -E..E; count = min(m -
+ * covered, E + 1) (the columns the runs leave uncovered, an edit estimate)
+ * and accept = count <= E.  The thesis's test after the first extraction
+ * (reject when the longest run is shorter than ceil((m - E) / (E + 1))) can
+ * only reject pairs the final test rejects, and changes neither output, so it
+ * is not repeated here.
+ * segs (optional, 3 (E + 1) ints): (diagonal, start column, length) of each
+ * run in the order found; *n_segs = their number. */
+int or_magnet(const uint8_t* read, const uint8_t* ref, int m, int E, int* count, int* segs, int* n_segs) {
+    uint8_t gone[OR_MAX_LEN];                     /* 1 = column left the search space */
+    memset(gone, 0, (size_t)m);
+    int covered = 0, ns = 0;
+    for (int it = 0; it <= E; ++it) {
+        int best = 0, best_c = 0, best_d = 0;
+        for (int c = 0; c < m; ++c)
+            for (int d = -E; d <= E; ++d) {
+                int L = 0;
+                while (c + L < m && !gone[c + L] && map_cell(read, ref, m, c + L, d, 1) == 0) L++;
+                if (L > best) { best = L; best_c = c; best_d = d; }
+            }
+        if (best == 0) break;
+        if (segs) { segs[3 * ns + 0] = best_d; segs[3 * ns + 1] = best_c; segs[3 * ns + 2] = best; }
+        ns++;
+        covered += best;
+        int a = best_c > 0 ? best_c - 1 : 0;
+        int b = best_c + best + 1 < m ? best_c + best + 1 : m;
+        for (int c = a; c < b; ++c) gone[c] = 1;
+    }
+    int left = m - covered;
+    if (n_segs) *n_segs = ns;
+    *count = left > E ? E + 1 : left;
+    return left <= E;
+}
+
+/* MAGNET over a batch (pairs as in or_filter_batch). */
+void or_magnet_batch(const uint8_t* reads, const uint8_t* refs, uint32_t stride, const uint16_t* len,
+                     const uint8_t* E, uint64_t n, uint8_t* acc, uint16_t* cnt, int nthreads) {
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 16)
+    for (int64_t i = 0; i < (int64_t)n; ++i) {
+        int c = 0;
+        acc[i] = (uint8_t)or_magnet(reads + (uint64_t)i * stride, refs + (uint64_t)i * stride, len[i], E[i],
+                                    &c, NULL, NULL);
+        cnt[i] = (uint16_t)c;
+    }
+}
+
 /* Levenshtein distance restricted to the 2E+1 diagonals around the main one
  * (Ukkonen's band, Sec. 2.2.2), for two strings of length m.  Returns
  * min(distance, E + 1).  When the true distance is at most E it equals the

@@ -438,3 +438,77 @@ def test_sneakysnake_t_E0_is_hamming_capped():
     for t in (1, 5, 10, 100):
         a, c = oracle.sneakysnake_t_batch(p.reads, p.refs, p.len, 0, t)
         assert np.array_equal(c, np.minimum(ham, 1)) and np.array_equal(a, (ham == 0).astype(np.uint8))
+
+
+# ---------------------------------------------------------------- MAGNET
+def test_magnet_identical_is_one_run():
+    p = pairgen.generate(pairgen.SMALL_100BP, 0, 50)
+    for i in range(p.n):
+        for E in (0, 3, 10):
+            assert oracle.magnet(p.reads[i], p.reads[i], E, with_segments=True) == (True, 0, [(0, 0, 100)])
+
+
+def _periodic_with_substitutions(m, subs):
+    # Reference ACGTACGT...: every diagonal with |d| in {1, 2, 3} mismatches
+    # everywhere.  A substitution to the base two steps on leaves diagonal 0
+    # blocked there and adds an isolated free cell on diagonals +-2 only.
+    ref = np.array([i % 4 for i in range(m)], np.uint8)
+    read = ref.copy()
+    for j in subs:
+        read[j] = (ref[j] + 2) % 4
+    return read, ref
+
+
+def test_magnet_isolated_substitutions_closed_form():
+    # The free runs of diagonal 0 are the gaps between substitutions; MAGNET
+    # takes the E+1 longest of them (each is longer than the isolated cells of
+    # diagonals +-2), and encapsulation drops exactly the substituted columns.
+    # So the uncovered columns are m minus the sum of the E+1 longest gaps.
+    rng = np.random.default_rng(21)
+    m = 100
+    for _ in range(300):
+        k = int(rng.integers(0, 9))
+        subs = []
+        while len(subs) < k:
+            j = int(rng.integers(0, m))
+            if all(abs(j - q) >= 3 for q in subs):
+                subs.append(j)
+        subs.sort()
+        read, ref = _periodic_with_substitutions(m, subs)
+        bounds = [-1] + subs + [m]
+        gaps = sorted((b - a - 1 for a, b in zip(bounds, bounds[1:]) if b - a - 1 > 0), reverse=True)
+        for E in (1, 2, 3):
+            left = m - sum(gaps[:E + 1])
+            acc, cnt, segs = oracle.magnet(read, ref, E, with_segments=True)
+            assert cnt == min(left, E + 1) and acc == (left <= E), (subs, E)
+            assert all(d == 0 for d, _, _ in segs)
+            if k <= E:
+                assert cnt == k
+
+
+def test_magnet_E0_accepts_only_exact_matches():
+    p = pairgen.generate(pairgen.SMALL_100BP, 0, 2000)
+    acc, cnt = oracle.magnet_batch(p.reads, p.refs, p.len, 0)
+    ham = (p.reads != p.refs).sum(1)
+    assert np.array_equal(acc, (ham == 0).astype(np.uint8))
+    assert np.array_equal(cnt, np.minimum(ham, 1))
+
+
+def test_magnet_runs_are_disjoint_longest_first_and_free():
+    # Invariants of extraction + encapsulation: every run found is free on its
+    # diagonal, runs never touch (one column at least between them), they come
+    # longest first, there are at most E+1, and the count is what they leave.
+    p = pairgen.generate(pairgen.SMALL_100BP, 5, 300)
+    for i in range(p.n):
+        for E in (2, 5):
+            acc, cnt, segs = oracle.magnet(p.reads[i], p.refs[i], E, with_segments=True)
+            Z = _maze(p.reads[i], p.refs[i], E)
+            assert 1 <= len(segs) <= E + 1
+            lens = [L for _, _, L in segs]
+            assert lens == sorted(lens, reverse=True)
+            spans = sorted((s, s + L) for _, s, L in segs)
+            assert all(b1 < a2 for (_, b1), (a2, _) in zip(spans, spans[1:]))
+            for d, s, L in segs:
+                assert not Z[d + E, s:s + L].any()
+            left = 100 - sum(lens)
+            assert cnt == min(left, E + 1) and acc == (left <= E)
