@@ -153,7 +153,7 @@ def main():
                          "on one map; uneven: 50M pairs of mixed lengths in the persistent launch, default "
                          "vs autotuned layout; learned-uneven: the same batch, learned-bucketed vs plain; "
                          "stream: 200M pairs streamed from pinned host memory in 8M-pair chunks; "
-                         "partitioned: SneakySnake on sub-mazes of t = 5, 10, 25, 50 columns vs the whole maze "
+                         "filters also times MAGNET; partitioned: SneakySnake on sub-mazes of t = 5, 10, 25, 50 columns vs the whole maze "
                          "at E = 0, 5, 10, 25; verify: banded edit distance of the pairs SneakySnake accepts "
                          "(filter + verify) vs verifying every pair, at E = 5, 10, 25")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -354,6 +354,14 @@ def filters_workload(args):
             gbs = n * (2 * W * 8 + nf * (2 + 1 / 8)) / (ms / 1e3) / 1e9
             row[name] = {"ms": round(ms, 4), "pairs_per_s": n / (ms / 1e3), "hbm_GBps": round(gbs, 1)}
             del out
+        out = ctx.alloc_out(n, SS, dev)
+        per, _, _ = time_steps(lambda: ctx.filter_magnet(b, out=out), steps, args.warmup)
+        ctx.check()
+        ms = sum(per) / len(per)
+        row["magnet"] = {"ms": round(ms, 4), "pairs_per_s": n / (ms / 1e3),
+                         "hbm_GBps": round(n * (2 * W * 8 + 2 + 1 / 8) / (ms / 1e3) / 1e9, 1),
+                         "accept_rate": round(float(paf.accept_bits_to_bool(out[SS][0], n).float().mean()), 5)}
+        del out
         by_E[str(E)] = row
         log(f"E={E}: " + ", ".join(f"{k} {v['ms']:.3f} ms" for k, v in row.items()))
     r10 = by_E["10"]["all three"]

@@ -146,6 +146,18 @@ paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, co
 paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t t, const paf_out* out,
                                   void* stream);
 
+/* MAGNET decision stage (Ch. 7) on the neighbourhood map of Ch. 6 (vacant
+ * cells blocked).  Repeatedly, up to E+1 times: the longest run of free cells
+ * over all 2E+1 diagonals among the columns still searched (extraction; ties
+ * go to the smallest start column, then to the first diagonal in order
+ * -E..E) is taken, and its columns plus one column on each side leave the
+ * search of every diagonal (encapsulation), until no free cell is left.
+ * count = min(m - columns covered by the runs, E+1), accept = count <= E
+ * (the thesis rejects when the runs cover fewer than m - E columns).  Unlike
+ * SneakySnake, MAGNET may reject a pair within E edits (Sec. 9.3.3).  Writes
+ * out->accept_bits[0] and out->count[0] (the other slots are ignored). */
+paf_status paf_filter_magnet(paf_ctx* ctx, const paf_batch* batch, const paf_out* out, void* stream);
+
 /* Verification of filtered pairs: dist[p] = min(edit distance, E+1) of the
  * pair's reference segment and read, over alignments that stay inside the
  * band of the 2E+1 diagonals the filter examined (Ukkonen's banded edit

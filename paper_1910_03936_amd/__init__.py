@@ -28,7 +28,7 @@ STATUS = {0: "PAF_OK", 1: "PAF_ERR_ARG", 2: "PAF_ERR_RANGE", 3: "PAF_ERR_DEVICE"
 
 # Every symbol declared in include/paf.h.
 EXPORTS = ("paf_create", "paf_destroy", "paf_last_error", "paf_check", "paf_pack", "paf_pack_host",
-           "paf_filter", "paf_filter_partitioned", "paf_verify", "paf_filter_persistent", "paf_autotune", "paf_set_layout", "paf_features",
+           "paf_filter", "paf_filter_partitioned", "paf_filter_magnet", "paf_verify", "paf_filter_persistent", "paf_autotune", "paf_set_layout", "paf_features",
            "paf_mlp_set_params", "paf_mlp_get_params", "paf_mlp_forward", "paf_mlp_train_step",
            "paf_mlp_predict", "paf_mlp_train", "paf_bucket", "paf_filter_ordered", "paf_filter_bucketed",
            "paf_filter_bucketed_local", "paf_cost_levels", "paf_filter_keyed", "paf_stream_filter")
@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH):
         "paf_filter_persistent": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
         "paf_filter_partitioned": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
         "paf_verify": ([P, ctypes.POINTER(_Batch), P, P, P]),
+        "paf_filter_magnet": ([P, ctypes.POINTER(_Batch), ctypes.POINTER(_Out), P]),
         "paf_autotune": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P,
                           ctypes.POINTER(Layout), ctypes.POINTER(ctypes.c_float),
                           ctypes.POINTER(ctypes.c_float)]),
@@ -270,6 +271,13 @@ class Context:
         out = out or self.alloc_out(batch.n_pairs, SNEAKYSNAKE, batch.device)
         cb, co = batch.c(), self._out(out)
         _check(self.lib.paf_filter_partitioned(self.h, ctypes.byref(cb), t, ctypes.byref(co), _stream(stream)))
+        return out
+
+    def filter_magnet(self, batch: Batch, out: dict | None = None, stream=None) -> dict:
+        """MAGNET's decision (accept bits and count in the SneakySnake slot)."""
+        out = out or self.alloc_out(batch.n_pairs, SNEAKYSNAKE, batch.device)
+        cb, co = batch.c(), self._out(out)
+        _check(self.lib.paf_filter_magnet(self.h, ctypes.byref(cb), ctypes.byref(co), _stream(stream)))
         return out
 
     def verify(self, batch: Batch, select_bits: torch.Tensor | None = None, dist: torch.Tensor | None = None,

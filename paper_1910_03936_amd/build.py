@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpaf.so")
-SOURCES = ["filter.hip", "whole.hip", "mlp.hip", "api.hip", "stream.hip", "verify.hip"]
+SOURCES = ["filter.hip", "whole.hip", "mlp.hip", "api.hip", "stream.hip", "verify.hip", "magnet.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -459,6 +459,20 @@ paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t
     return PAF_OK;
 }
 
+paf_status paf_filter_magnet(paf_ctx* ctx, const paf_batch* batch, const paf_out* out, void* stream) {
+    const uint32_t filters = PAF_SNEAKYSNAKE;   // output slot 0
+    FilterParams p;
+    paf_status st = check_batch(ctx, batch, filters, p);
+    if (st != PAF_OK) return st;
+    if ((st = check_out(out, filters)) != PAF_OK) return st;
+    const int emax = emax_bucket((int)p.max_E);
+    if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
+    set_outputs(p, out);
+    PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    PAF_HIP(launch_magnet(p, emax, (hipStream_t)stream), "MAGNET launch");
+    return PAF_OK;
+}
+
 paf_status paf_verify(paf_ctx* ctx, const paf_batch* batch, const uint32_t* select_bits, uint16_t* dist,
                       void* stream) {
     FilterParams p;
