@@ -155,7 +155,9 @@ paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t
  * count = min(m - columns covered by the runs, E+1), accept = count <= E
  * (the thesis rejects when the runs cover fewer than m - E columns).  Unlike
  * SneakySnake, MAGNET may reject a pair within E edits (Sec. 9.3.3).  Writes
- * out->accept_bits[0] and out->count[0] (the other slots are ignored). */
+ * out->accept_bits[0] and out->count[0] (the other slots are ignored).  Uses
+ * the context's bucketing workspace (5 bytes per pair, grown on first use
+ * with a larger batch). */
 paf_status paf_filter_magnet(paf_ctx* ctx, const paf_batch* batch, const paf_out* out, void* stream);
 
 /* Verification of filtered pairs: dist[p] = min(edit distance, E+1) of the

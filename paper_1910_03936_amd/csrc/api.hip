@@ -469,7 +469,10 @@ paf_status paf_filter_magnet(paf_ctx* ctx, const paf_batch* batch, const paf_out
     if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
     set_outputs(p, out);
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    PAF_HIP(launch_magnet(p, emax, (hipStream_t)stream), "MAGNET launch");
+    if ((st = ensure_bucket_ws(ctx, p.n_pairs)) != PAF_OK) return st;
+    PAF_HIP(launch_magnet(p, emax, ctx->ws_bucket, ctx->ws_counts, ctx->ws_perm, ctx->ws_hist, ctx->num_cus,
+                          (hipStream_t)stream),
+            "MAGNET launch");
     return PAF_OK;
 }
 

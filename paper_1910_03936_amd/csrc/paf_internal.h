@@ -86,8 +86,10 @@ size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_
 // words, or NULL for every pair).
 hipError_t launch_verify(const FilterParams& p, int emax, const uint32_t* sel, uint16_t* dist, hipStream_t s);
 
-// magnet.hip: MAGNET counts into p.cnt[0], then accept bits into p.acc[0].
-hipError_t launch_magnet(const FilterParams& p, int emax, hipStream_t s);
+// magnet.hip: MAGNET counts into p.cnt[0], then accept bits into p.acc[0];
+// flag/counts/order/hist: the bucketing workspace (flag: n_pairs bytes).
+hipError_t launch_magnet(const FilterParams& p, int emax, uint8_t* flag, uint32_t* counts, uint32_t* order,
+                         uint32_t* hist, int num_cus, hipStream_t s);
 
 // mlp.hip
 struct MlpDev {
