@@ -1,11 +1,11 @@
 """CPU oracle -- TEST INFRASTRUCTURE ONLY.
 
 Plain, slow, obviously-correct implementations of what the GPU path computes
-(SneakySnake on the unweighted and weighted maze and on a column-partitioned
-maze, GateKeeper, Shouji, MAGNET, banded and full Levenshtein distance, the
-cost-model features, and the cost-model MLP in float64).  Only the tests, the
-package's smoke check and the benchmark's CPU baseline leg may import this
-package; the product path never does.  It shares
+(SneakySnake on the unweighted and weighted maze, on a column-partitioned maze
+and in its hardware form, GateKeeper, Shouji, MAGNET, banded and full
+Levenshtein distance, the cost-model features, and the cost-model MLP in
+float64).  Only the tests, the package's smoke check and the benchmark's CPU
+baseline leg may import this package; the product path never does.  It shares
 no code with the GPU library: the C part (oracle.c) is compiled by gcc into its
 own shared object, and the MLP reference (mlp.py) is numpy.
 """
@@ -48,6 +48,9 @@ def _load():
         lib.or_sneakysnake_weighted.argtypes = [P, P, I, I, P]
         lib.or_sneakysnake_t.argtypes = [P, P, I, I, I, P]
         lib.or_magnet.argtypes = [P, P, I, I, P, P, P]
+        lib.or_sneakysnake_fpga.argtypes = [P, P, I, I, I, I, P]
+        lib.or_sneakysnake_fpga_batch.argtypes = [P, P, ctypes.c_uint32, P, P, ctypes.c_uint64, I, I, P, P, I]
+        lib.or_sneakysnake_fpga_batch.restype = None
         lib.or_magnet_batch.argtypes = [P, P, ctypes.c_uint32, P, P, ctypes.c_uint64, P, P, I]
         lib.or_magnet_batch.restype = None
         lib.or_sneakysnake_t_batch.argtypes = [P, P, ctypes.c_uint32, P, P, ctypes.c_uint64, I, P, P, I]
@@ -111,6 +114,28 @@ def sneakysnake_t(read, ref, E, t):
     cnt = ctypes.c_int(0)
     acc = lib.or_sneakysnake_t(_p(rd), _p(rf), rd.shape[0], E, t, ctypes.byref(cnt))
     return bool(acc), cnt.value
+
+
+def sneakysnake_fpga(read, ref, E, t, y):
+    """(accept, count) of the hardware form: sub-mazes of t columns, y replications each."""
+    lib = _load()
+    rd, rf = _u8(read), _u8(ref)
+    cnt = ctypes.c_int(0)
+    acc = lib.or_sneakysnake_fpga(_p(rd), _p(rf), rd.shape[0], E, t, y, ctypes.byref(cnt))
+    return bool(acc), cnt.value
+
+
+def sneakysnake_fpga_batch(reads, refs, lens, Es, t, y, threads=None):
+    lib = _load()
+    reads, refs = _u8(reads), _u8(refs)
+    n, stride = reads.shape
+    lens = np.ascontiguousarray(np.asarray(lens, np.uint16))
+    Es = np.ascontiguousarray(np.broadcast_to(np.asarray(Es, np.uint8), (n,)))
+    a = np.zeros(n, np.uint8)
+    c = np.zeros(n, np.uint16)
+    lib.or_sneakysnake_fpga_batch(_p(reads), _p(refs), stride, _p(lens), _p(Es), n, int(t), int(y), _p(a), _p(c),
+                                  _threads(threads))
+    return a, c
 
 
 def magnet(read, ref, E, with_segments=False):

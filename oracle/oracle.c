@@ -126,6 +126,40 @@ int or_sneakysnake_t(const uint8_t* read, const uint8_t* ref, int m, int E, int 
     return e <= E;
 }
 
+/* The hardware form of SneakySnake (Sec. 8.6): sub-mazes of t columns (the
+ * last one narrower when t does not divide m), each searched by y
+ * replications of three steps: a leading-zero count of every row from the
+ * current column (the search starts at a row's least significant bit, and
+ * bits shifted in past the sub-maze's end are ones), the largest count x over
+ * the rows, and a shift of every row by x + 1.  A sub-maze of width w then
+ * counts min(y, w - sum of its x) obstacles.  The pair's count is min(sum over
+ * the sub-mazes, E + 1); accept = sum <= E.
+ * Reading: the text also says a sub-maze counts y obstacles whenever every
+ * replication found x > 0, which gives 2 for its own step-4 example (one row
+ * 00010000, t = 8, y = 2: x = 4 then 3, one obstacle); min(y, w - sum x)
+ * gives 1 and is used for every sub-maze. */
+int or_sneakysnake_fpga(const uint8_t* read, const uint8_t* ref, int m, int E, int t, int y, int* count) {
+    int e = 0;
+    for (int p0 = 0; p0 < m; p0 += t) {
+        int p1 = p0 + t < m ? p0 + t : m;
+        int c = p0, sx = 0;
+        for (int r = 0; r < y; ++r) {
+            int x = 0;
+            for (int d = -E; d <= E; ++d) {
+                int L = 0;
+                while (c + L < p1 && map_cell(read, ref, m, c + L, d, 1) == 0) L++;
+                if (L > x) x = L;
+            }
+            sx += x;
+            c += x + 1;
+        }
+        int ob = (p1 - p0) - sx;
+        e += ob < y ? ob : y;
+    }
+    *count = e > E ? E + 1 : e;
+    return e <= E;
+}
+
 /* SneakySnake on the weighted maze (Sec. 8.3, Eq. 8.1): each available cell holds the
  * number of available cells from it to the end of its pipe, filled from the
  * lower right; the snake reads the largest weight in its column instead of
@@ -408,6 +442,20 @@ void or_sneakysnake_t_batch(const uint8_t* reads, const uint8_t* refs, uint32_t 
         int c = 0;
         acc[i] = (uint8_t)or_sneakysnake_t(reads + (uint64_t)i * stride, refs + (uint64_t)i * stride,
                                            len[i], E[i], t, &c);
+        cnt[i] = (uint16_t)c;
+    }
+}
+
+/* Hardware-form SneakySnake over a batch (pairs as in or_filter_batch). */
+void or_sneakysnake_fpga_batch(const uint8_t* reads, const uint8_t* refs, uint32_t stride, const uint16_t* len,
+                               const uint8_t* E, uint64_t n, int t, int y, uint8_t* acc, uint16_t* cnt,
+                               int nthreads) {
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 256)
+    for (int64_t i = 0; i < (int64_t)n; ++i) {
+        int c = 0;
+        acc[i] = (uint8_t)or_sneakysnake_fpga(reads + (uint64_t)i * stride, refs + (uint64_t)i * stride, len[i],
+                                              E[i], t, y, &c);
         cnt[i] = (uint16_t)c;
     }
 }

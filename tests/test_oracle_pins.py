@@ -512,3 +512,51 @@ def test_magnet_runs_are_disjoint_longest_first_and_free():
                 assert not Z[d + E, s:s + L].any()
             left = 100 - sum(lens)
             assert cnt == min(left, E + 1) and acc == (left <= E)
+
+
+# ---------------------------------------------------------------- hardware form (t columns, y replications)
+def test_fpga_tile_worked_example():
+    # Sec. 8.6 step 4: one row 00010000 (t = 8) searched by two replications
+    # finds x = 4 and x = 3, and the sub-maze holds one obstacle.
+    g = read_golden("lzc_tile.txt")
+    row = g["row_msb_first"][::-1]
+    m = len(row)
+    ref = np.array([i % 4 for i in range(m)], np.uint8)
+    read = ref.copy()
+    for c, bit in enumerate(row):
+        if bit == "1":
+            read[c] = (ref[c] + 2) % 4
+    assert oracle.sneakysnake_fpga(read, ref, 1, 8, 2) == (True, int(g["obstacles"]))
+    # One replication finds the first pipe only: min(1, 8 - 4) = 1.
+    assert oracle.sneakysnake_fpga(read, ref, 1, 8, 1) == (True, 1)
+
+
+def test_fpga_tile_counts_least_obstacles_capped_by_replications():
+    # Each replication crosses at most one obstacle, and the greedy is optimal
+    # in a sub-maze (Sec. 8.6), so a sub-maze counts min(y, its fewest
+    # obstacles): checked against the dynamic programme over every pipe.
+    rng = np.random.default_rng(31)
+    for _ in range(400):
+        m = int(rng.integers(1, 30))
+        E = int(rng.integers(0, 4))
+        a = rng.integers(0, 4, m).astype(np.uint8)
+        b = a.copy()
+        for _ in range(int(rng.integers(0, 8))):
+            b[int(rng.integers(0, m))] = rng.integers(0, 4)
+        if rng.random() < 0.5 and m > 2:
+            i = int(rng.integers(0, m))
+            b = np.concatenate([b[:i], b[i + 1:], rng.integers(0, 4, 1)]).astype(np.uint8)
+        Z = _maze(a, b, E)
+        for t in (3, 5, 8):
+            for y in (1, 2, 3, 8):
+                total = sum(min(y, _least_obstacles(Z, p0, min(p0 + t, m))) for p0 in range(0, m, t))
+                assert oracle.sneakysnake_fpga(a, b, E, t, y) == (total <= E, min(total, E + 1)), (m, E, t, y)
+
+
+def test_fpga_tile_enough_replications_is_partitioned_maze():
+    p = pairgen.generate(pairgen.SMALL_100BP, 3, 1500)
+    for E in (2, 5):
+        for t in (5, 8):
+            a, c = oracle.sneakysnake_fpga_batch(p.reads, p.refs, p.len, E, t, t)
+            a2, c2 = oracle.sneakysnake_t_batch(p.reads, p.refs, p.len, E, t)
+            assert np.array_equal(a, a2) and np.array_equal(c, c2)
