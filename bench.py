@@ -521,6 +521,10 @@ def next_workloads(args):
                 ms = timed(lambda: ctx.filter_partitioned(b, tp, out=out))
                 acc = float(paf.accept_bits_to_bool(out[SS][0], n).float().mean())
                 row[f"t={tp}"] = {"ms": round(ms, 4), "accept_rate": round(acc, 5)}
+            # The hardware form: sub-mazes of 8 columns, 3 replications each.
+            ms = timed(lambda: ctx.filter_partitioned(b, 8, 3, out=out))
+            acc = float(paf.accept_bits_to_bool(out[SS][0], n).float().mean())
+            row["t=8, y=3"] = {"ms": round(ms, 4), "accept_rate": round(acc, 5)}
             by_E[str(E)] = row
             log(f"E={E}: " + ", ".join(f"{k} {v['ms']:.3f} ms (acc {v['accept_rate']:.4f})" for k, v in row.items()))
         r = by_E["10"]["t=5"]

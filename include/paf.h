@@ -136,15 +136,22 @@ paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, co
  * solved on its own by the greedy of paf_filter: a pipe is probed only up to
  * the sub-maze's last column, reaching that column costs nothing, and the
  * snake enters the next sub-maze free to take any diagonal.  The obstacles of
- * all sub-mazes add up: count = min(sum, E+1), accept = sum <= E.  The count
- * never exceeds the whole maze's (so there are no false rejects either), and
- * t >= m gives paf_filter's SneakySnake result.  t in [1, PAF_MAX_PART].
- * Writes out->accept_bits[0] and out->count[0] (the SneakySnake slots; the
- * others are ignored).  Runs on the compacting engine with paf_filter's
- * layout (a forced layout applies when its chunk_tiles > 0). */
+ * all sub-mazes add up: count = min(sum, E+1), accept = sum <= E.
+ * y = 0: no other limit (SneakySnake-t).  y in [1, PAF_MAX_REPL]: the
+ * hardware form of Sec. 8.6 (t = 8, y = 3 there), which searches each
+ * sub-maze with y replications of leading-zero count, maximum and shift by
+ * x + 1 and counts min(y, w - sum x) obstacles in a sub-maze of width w; that
+ * is min(y, the sub-maze's fewest obstacles), which is what is computed.
+ * The count never exceeds the whole maze's (so there are no false rejects
+ * either), and t >= m with y = 0 gives paf_filter's SneakySnake result.
+ * t in [1, PAF_MAX_PART].  Writes out->accept_bits[0] and out->count[0] (the
+ * SneakySnake slots; the others are ignored).  Runs on the compacting engine
+ * with paf_filter's layout (a forced layout applies when its chunk_tiles >
+ * 0). */
 #define PAF_MAX_PART 65535
-paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t t, const paf_out* out,
-                                  void* stream);
+#define PAF_MAX_REPL 31
+paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t t, uint32_t y,
+                                  const paf_out* out, void* stream);
 
 /* MAGNET decision stage (Ch. 7) on the neighbourhood map of Ch. 6 (vacant
  * cells blocked).  Repeatedly, up to E+1 times: the longest run of free cells

@@ -21,6 +21,7 @@ SNEAKYSNAKE, GATEKEEPER, SHOUJI = 1, 2, 4
 ALL_FILTERS = SNEAKYSNAKE | GATEKEEPER | SHOUJI
 MAX_LEN, MAX_E = 512, 31
 MAX_PART = 65535  # widest sub-maze of paf_filter_partitioned
+MAX_REPL = 31     # most replications (obstacles per sub-maze) of paf_filter_partitioned
 MLP_NPARAMS = 24961
 
 STATUS = {0: "PAF_OK", 1: "PAF_ERR_ARG", 2: "PAF_ERR_RANGE", 3: "PAF_ERR_DEVICE",
@@ -94,7 +95,7 @@ def load_library(path: str = LIB_PATH):
         "paf_pack_host": ([P, U32, P, ctypes.c_uint16, P, U32, U64, P, I]),
         "paf_filter": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
         "paf_filter_persistent": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
-        "paf_filter_partitioned": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
+        "paf_filter_partitioned": ([P, ctypes.POINTER(_Batch), U32, U32, ctypes.POINTER(_Out), P]),
         "paf_verify": ([P, ctypes.POINTER(_Batch), P, P, P]),
         "paf_filter_magnet": ([P, ctypes.POINTER(_Batch), ctypes.POINTER(_Out), P]),
         "paf_autotune": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P,
@@ -266,11 +267,13 @@ class Context:
         _check(self.lib.paf_filter(self.h, ctypes.byref(cb), filters, ctypes.byref(co), _stream(stream)))
         return out
 
-    def filter_partitioned(self, batch: Batch, t: int, out: dict | None = None, stream=None) -> dict:
-        """SneakySnake on the maze cut into sub-mazes of t columns."""
+    def filter_partitioned(self, batch: Batch, t: int, y: int = 0, out: dict | None = None, stream=None) -> dict:
+        """SneakySnake on the maze cut into sub-mazes of t columns; y > 0: at
+        most y obstacles per sub-maze (the hardware form's y replications)."""
         out = out or self.alloc_out(batch.n_pairs, SNEAKYSNAKE, batch.device)
         cb, co = batch.c(), self._out(out)
-        _check(self.lib.paf_filter_partitioned(self.h, ctypes.byref(cb), t, ctypes.byref(co), _stream(stream)))
+        _check(self.lib.paf_filter_partitioned(self.h, ctypes.byref(cb), t, y, ctypes.byref(co),
+                                               _stream(stream)))
         return out
 
     def filter_magnet(self, batch: Batch, out: dict | None = None, stream=None) -> dict:

@@ -427,18 +427,20 @@ paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, co
     return PAF_OK;
 }
 
-paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t t, const paf_out* out,
-                                 void* stream) {
+paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t t, uint32_t y,
+                                  const paf_out* out, void* stream) {
     const uint32_t filters = PAF_SNEAKYSNAKE;
     FilterParams p;
     paf_status st = check_batch(ctx, batch, filters, p);
     if (st != PAF_OK) return st;
     if ((st = check_out(out, filters)) != PAF_OK) return st;
     if (t < 1 || t > PAF_MAX_PART) return fail(PAF_ERR_RANGE, "partition width outside [1, PAF_MAX_PART]");
+    if (y > PAF_MAX_REPL) return fail(PAF_ERR_RANGE, "replications outside [0, PAF_MAX_REPL]");
     const int emax = emax_bucket((int)p.max_E);
     if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
     set_outputs(p, out);
     p.part = t;
+    p.part_cap = y ? y : ~0u;
     const bool general = batch->len || batch->E || batch->word_offset;
     // The compacting engine, as a full grid of chunks (a forced layout that
     // compacts sets the chunk size, block shape and pass widths).

@@ -128,19 +128,20 @@ __device__ void snake_tile(const FilterParams& P, uint64_t tile, int lane, uint6
 // but the list lives in LDS.
 //
 // List entry (64 bits): pair index in the chunk (10 bits), column c (9),
-// edits e (5), continuation flag (1), m (10), E (5); plus the dead-diagonal
+// edits e (5), continuation flag (1), m (10), E (5), and for a partitioned
+// maze the edits counted in the current sub-maze (5); plus the dead-diagonal
 // mask of a snake that entered the window inside a pipe, and (general
 // layout) the pair's word offset.
 constexpr uint32_t kChunkMaxTiles = 16;
 
 struct ChunkEntry {
-    uint32_t idx, c, e, m, E;
+    uint32_t idx, c, e, m, E, ep;
     bool cont;
 };
 
 __device__ __forceinline__ uint64_t chunk_pack(const ChunkEntry& t) {
     return (uint64_t)t.idx | ((uint64_t)t.c << 10) | ((uint64_t)t.e << 19) | ((uint64_t)t.cont << 24) |
-           ((uint64_t)t.m << 25) | ((uint64_t)t.E << 35);
+           ((uint64_t)t.m << 25) | ((uint64_t)t.E << 35) | ((uint64_t)min(t.ep, 31u) << 40);
 }
 
 __device__ __forceinline__ ChunkEntry chunk_unpack(uint64_t v) {
@@ -151,6 +152,7 @@ __device__ __forceinline__ ChunkEntry chunk_unpack(uint64_t v) {
     t.cont = ((v >> 24) & 1u) != 0;
     t.m = (uint32_t)(v >> 25) & 1023u;
     t.E = (uint32_t)(v >> 35) & 31u;
+    t.ep = (uint32_t)(v >> 40) & 31u;
     return t;
 }
 
@@ -216,7 +218,11 @@ struct ChunkLds {
 // PART: the maze is cut into sub-mazes of P.part columns, each solved on its
 // own (Sec. 8.6; SneakySnake-t of Sec. 9.3.1).  A lane then also tracks pe,
 // the first column of the next sub-maze: a probe's run is cut at pe, reaching
-// pe costs nothing, and the snake leaves pe free to take any diagonal.
+// pe costs nothing, and the snake leaves pe free to take any diagonal.  With
+// a cap y (P.part_cap), a sub-maze counts at most y obstacles: the hardware's
+// y replications each cross one, so after the y-th the snake moves on to pe
+// (a sub-maze then counts min(y, its fewest obstacles), the hardware's
+// min(y, w - sum x)).
 template <int EMAX, bool GENERAL, bool PART>
 __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, int lane,
                             const ChunkLds<EMAX, GENERAL>& L) {
@@ -352,6 +358,7 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
             // sub-maze's first column (reaching that column ends the pipe), so
             // pe follows from c alone.
             uint32_t pe = PART ? (c / P.part + 1u) * P.part : 0u;
+            uint32_t ep = t.ep;
             for (uint32_t wk = w; wk < w + span && wave_any(act); ++wk) {
                 const WindowWords q = window_words_direct(P.reads + off, P.refs + off, (int)wk, W, (int)m);
                 // Vacant cells only occur in the first window and near the
@@ -410,9 +417,14 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                         const uint32_t R = c + (uint32_t)__builtin_popcount(runs);
                         const uint32_t at = R == pe ? 1u : 0u;
                         clear = (runs >> 31) & (at ^ 1u);
-                        e += ((R - m) >> 31) & ((clear | at) ^ 1u);
+                        const uint32_t ob = ((R - m) >> 31) & ((clear | at) ^ 1u);
+                        e += ob;
+                        ep += ob;
                         c = R + 1u - clear - at;
-                        pe += c == pe ? P.part : 0u;
+                        c = ep >= P.part_cap ? pe : c;
+                        const bool nx = c == pe;
+                        pe += nx ? P.part : 0u;
+                        ep = nx ? 0u : ep;
                     } else {
                         clear = runs >> 31;
                         // The obstacle's column; when a pipe runs past the
@@ -467,6 +479,7 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                 u.c = c;
                 u.e = e;
                 u.cont = cont;
+                u.ep = PART ? ep : 0u;
                 L.ent[n_out + pre] = chunk_pack(u);
                 L.dead[n_out + pre] = dead;
             }

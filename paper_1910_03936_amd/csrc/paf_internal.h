@@ -43,6 +43,7 @@ struct FilterParams {
     const uint8_t* order_key;  // compacting engine: per-pair key (original order); each chunk's
                                // pairs enter the first window in ascending key order, or NULL
     uint32_t part;             // compacting engine, partitioned maze: sub-maze width in columns
+    uint32_t part_cap;         // ... and the most obstacles one sub-maze counts (~0u: no cap)
 };
 
 // Kernel selection.

@@ -94,3 +94,53 @@ def test_partitioned_range_errors(ctx):
     for t in (0, paf.MAX_PART + 1):
         with pytest.raises(paf.PafError):
             ctx.filter_partitioned(b, t)
+
+
+def _want_fpga(p, t, y):
+    a, c = oracle.sneakysnake_fpga_batch(p.reads, p.refs, p.len, p.E, t, y)
+    return {SS: (a, c)}
+
+
+@pytest.mark.parametrize("E", [0, 5, 10, 25])
+def test_hardware_form_fixed_250bp(ctx, E):
+    """The hardware form (t-column sub-mazes, y replications each) against the
+    oracle that follows its steps: leading-zero counts, maximum, shift."""
+    p = pairgen.generate(pairgen.FIXED_250BP.with_E(E), 73, 64 * 19 + 3)
+    b = to_device(p, ctx, per_pair=False, offsets=False)
+    for t, y in ((8, 3), (8, 1), (8, 2), (5, 1), (10, 3), (32, 4), (33, 2), (64, 31)):
+        want = _want_fpga(p, t, y)
+        assert_parity(results(ctx.filter_partitioned(b, t, y), p.n), want, f"E={E} t={t} y={y}")
+        ctx.set_layout(_layout(2, 0, 5, 2, 3))
+        assert_parity(results(ctx.filter_partitioned(b, t, y), p.n), want, f"E={E} t={t} y={y} spans 2,3")
+        ctx.set_layout(None)
+    ctx.check()
+
+
+def test_hardware_form_uneven_and_edges(ctx):
+    p = pairgen.generate(pairgen.UNEVEN_MIX, 79, 4000)
+    b = to_device(p, ctx, per_pair=True, offsets=True)
+    for t, y in ((8, 3), (5, 2), (16, 1)):
+        assert_parity(results(ctx.filter_partitioned(b, t, y), p.n), _want_fpga(p, t, y), f"uneven t={t} y={y}")
+    rng = np.random.default_rng(83)
+    rows = []
+    for m in (1, 7, 8, 9, 31, 32, 33, 64, 65, 255, 256, 257, 512):
+        a = rng.integers(0, 4, m).astype(np.uint8)
+        b2 = a.copy()
+        b2[rng.integers(0, m, max(1, m // 12))] ^= 1
+        for ref in (a, b2, np.roll(a, 1), (a + 2) % 4):
+            for E in sorted({0, 3, 15, min(31, m), 31}):
+                rows.append((a, ref, m, E))
+    n = len(rows)
+    R = np.zeros((n, 512), np.uint8)
+    F = np.zeros((n, 512), np.uint8)
+    L = np.zeros(n, np.uint16)
+    Ev = np.zeros(n, np.uint8)
+    for i, (a, r, m, E) in enumerate(rows):
+        R[i, :m], F[i, :m], L[i], Ev[i] = a, r, m, E
+    q = pairgen.Pairs(R, F, L, Ev, np.zeros(n, np.uint8), np.zeros(n, np.uint16))
+    bq = to_device(q, ctx, per_pair=True, offsets=True, max_len=512, max_E=31)
+    for t, y in ((8, 3), (1, 1), (3, 2), (40, 5)):
+        assert_parity(results(ctx.filter_partitioned(bq, t, y), q.n), _want_fpga(q, t, y), f"edges t={t} y={y}")
+    with pytest.raises(paf.PafError):
+        ctx.filter_partitioned(bq, 8, paf.MAX_REPL + 1)
+    ctx.check()
