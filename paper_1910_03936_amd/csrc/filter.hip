@@ -385,33 +385,34 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                         if ((uint32_t)(dd < 0 ? -dd : dd) > E) M[d] = 0u;
                     }
                 }
-                // The snake state stays in plain integers (column c, edits e,
-                // whether the last probe ran through the window's end and the
-                // bit it started from), so the loop carries no lane masks
-                // beyond its own condition: the lane probes while c is inside
-                // both the window and the pair and e <= E.
-                const uint32_t w0 = 32u * wk, w31 = w0 + 31u;
-                const uint32_t lim = min(m, w0 + 32u);
+                const uint32_t w0 = 32u * wk;
                 const bool live = act;
                 uint32_t clear = 0, bs = 0;
-                while (act && (int32_t)((c - lim) & (e - E - 1u)) < 0) {
-                    // Pipes from column c: adding 1 << s to a match word
-                    // carries through its run of free cells from s, so
-                    // Z & ~(Z + (1 << s)) is that run; the OR over the
-                    // diagonals is [s, s + deepest run), with bit 31 set when a
-                    // pipe reaches the window's end.
-                    bs = 0x80000000u >> (w31 - c);
-                    uint32_t r0 = 0, r1 = 0;
+                if constexpr (PART) {
+                    // The snake state stays in plain integers (column c,
+                    // edits e, the sub-maze's end pe and its edits ep), so the
+                    // loop carries no lane masks beyond its own condition: the
+                    // lane probes while c is inside both the window and the
+                    // pair and e <= E.
+                    const uint32_t w31 = w0 + 31u;
+                    const uint32_t lim = min(m, w0 + 32u);
+                    while (act && (int32_t)((c - lim) & (e - E - 1u)) < 0) {
+                        // Pipes from column c: adding 1 << s to a match word
+                        // carries through its run of free cells from s, so
+                        // Z & ~(Z + (1 << s)) is that run; the OR over the
+                        // diagonals is [s, s + deepest run), with bit 31 set
+                        // when a pipe reaches the window's end.
+                        bs = 0x80000000u >> (w31 - c);
+                        uint32_t r0 = 0, r1 = 0;
 #pragma unroll
-                    for (int d = 0; d < D; d += 2) {
-                        r0 = or_andn(r0, M[d], M[d] + bs);
-                        if (d + 1 < D) r1 = or_andn(r1, M[d + 1], M[d + 1] + bs);
-                    }
-                    uint32_t runs = r0 | r1;
-                    if constexpr (PART) {
-                        // The run stops at the sub-maze's end pe; reaching
-                        // it is free (at), and so is the window's end when
-                        // pe lies beyond it (clear: the pipe goes on).
+                        for (int d = 0; d < D; d += 2) {
+                            r0 = or_andn(r0, M[d], M[d] + bs);
+                            if (d + 1 < D) r1 = or_andn(r1, M[d + 1], M[d + 1] + bs);
+                        }
+                        uint32_t runs = r0 | r1;
+                        // The run stops at the sub-maze's end pe; reaching it
+                        // is free (at), and so is the window's end when pe
+                        // lies beyond it (clear: the pipe goes on).
                         const uint32_t cut = pe - w0;
                         runs &= cut < 32u ? (1u << cut) - 1u : ~0u;
                         const uint32_t R = c + (uint32_t)__builtin_popcount(runs);
@@ -425,17 +426,39 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                         const bool nx = c == pe;
                         pe += nx ? P.part : 0u;
                         ep = nx ? 0u : ep;
-                    } else {
+                    }
+                } else {
+                    // Every lane still undecided enters the window at its
+                    // first column (it left the last one at its end), so the
+                    // snake's column lives in a one-hot word b: a probe from
+                    // b gives the run [s, s + L) as above, and runs + b is
+                    // the bit of the obstacle at s + L (zero when a pipe runs
+                    // through the window's end).  An obstacle inside the pair
+                    // costs one edit, and the next probe starts one column
+                    // after it.  The lane probes while b is a column of the
+                    // pair and e <= E.
+                    const uint32_t inpair = m >= w0 + 32u ? ~0u : (1u << (m - w0)) - 1u;
+                    uint32_t b = act ? 1u : 0u, runs = 0;
+                    while ((b & inpair) != 0u && e <= E) {
+                        uint32_t r0 = 0, r1 = 0;
+#pragma unroll
+                        for (int d = 0; d < D; d += 2) {
+                            r0 = or_andn(r0, M[d], M[d] + b);
+                            if (d + 1 < D) r1 = or_andn(r1, M[d + 1], M[d + 1] + b);
+                        }
+                        runs = r0 | r1;
+                        const uint32_t ob = runs + b;
+                        e += min(ob & inpair, 1u);
+                        b = ob << 1;
+                    }
+                    if (live) {
+                        // The column reached: past the pair's end inside the
+                        // window, or the next window's first column.
+                        c = b != 0u ? w0 + (uint32_t)__builtin_ctz(b) : w0 + 32u;
                         clear = runs >> 31;
-                        // The obstacle's column; when a pipe runs past the
-                        // window the run is [s, 32) and this is the window's
-                        // end.
-                        const uint32_t R = c + (uint32_t)__builtin_popcount(runs);
-                        // An obstacle inside the pair (R < m) counts one edit.
-                        e += ((R - m) >> 31) & (clear ^ 1u);
-                        // Cross the obstacle (R + 1), or stay at the window's
-                        // end inside the pipe (R).
-                        c = R + 1u - clear;
+                        // The last probe's start, for the dead-diagonal mask
+                        // of a pipe running on (its run is [s, 32)).
+                        bs = runs & (0u - runs);
                     }
                 }
                 // A lane is decided once it crossed the pair's end (accept
