@@ -220,7 +220,7 @@ def main():
 
     plain = {"value": plain_value, "ms_per_step": plain_ms,
              "roofline": roof(plain_kern_ms, plain_bytes_pair,
-                              f"chunk_kernel<E={args.E}, uniform> (compacting SneakySnake, 8-tile chunks)",
+                              f"chunk_kernel<E={args.E}, uniform> (compacting SneakySnake, 6-tile chunks, 2-window passes)",
                               f"snake_chunk_plain_250bp_E{args.E}")}
     rec_value, rec_ms, roofline, learned = plain_value, plain_ms, plain["roofline"], None
 
