@@ -9,7 +9,11 @@ every pair).
 - 50M pairs of mixed lengths in the persistent launch with the autotuned
   layout, the fixed per-tile layout and the learned local pipeline;
 - 200M pairs streamed from pinned host memory in 8M-pair chunks, plain and
-  learned.
+  learned;
+- the rows beyond the path on the 10M x 250 bp pairs: SneakySnake on
+  partitioned mazes (t = 5, 10, 25, 50) and in the hardware form (t = 8,
+  y = 3), MAGNET, and verification of SneakySnake's survivors (identical to
+  verifying every pair).
 """
 import numpy as np
 import pytest
@@ -115,3 +119,71 @@ def test_full_size_stream_200M(gpu_ctx):
     ids = pairgen.sample_ids(n, 20000)
     s = pairgen.generate_ids(w, ids)
     check_sample(out[True], s, ids, s.E, SS)
+
+
+def _sampled(got_acc, got_cnt, ids, want_acc, want_cnt, label):
+    ix = ids.astype(np.int64)
+    bad = np.nonzero((got_acc[ix] != want_acc) | (got_cnt[ix] != want_cnt))[0]
+    assert bad.size == 0, (f"{label}: {bad.size} sampled mismatches, first pair ids {ix[bad[:5]]}: "
+                           f"gpu {got_acc[ix][bad[:5]]}/{got_cnt[ix][bad[:5]]} oracle {want_acc[bad[:5]]}/"
+                           f"{want_cnt[bad[:5]]}")
+
+
+@pytest.mark.parametrize("E", [5, 10, 25])
+def test_full_size_partitioned_and_hardware_form(gpu_ctx, fixed250, E):
+    b, ids, s = fixed250
+    b.uniform_E = E
+    b.max_E = E
+    n = b.n_pairs
+    whole = results(gpu_ctx.filter(b, SS), n)[SS][1].astype(np.int64)
+    prev = None
+    for t, y in ((5, 0), (10, 0), (25, 0), (50, 0), (8, 3)):
+        acc, cnt = results(gpu_ctx.filter_partitioned(b, t, y), n)[SS]
+        check_properties({SS: (acc, cnt)}, E)
+        if y == 0:
+            wa, wc = oracle.sneakysnake_t_batch(s.reads, s.refs, s.len, E, t)
+            # no sub-maze count exceeds the whole maze's
+            assert np.all(cnt.astype(np.int64) <= whole)
+        else:
+            wa, wc = oracle.sneakysnake_fpga_batch(s.reads, s.refs, s.len, E, t, y)
+        _sampled(acc, cnt, ids, wa, wc, f"E={E} t={t} y={y}")
+        if t == 10:
+            # t = 5 refines t = 10: never more obstacles
+            assert np.all(prev <= cnt)
+        prev = cnt
+    gpu_ctx.check()
+
+
+@pytest.mark.parametrize("E", [5, 10])
+def test_full_size_magnet(gpu_ctx, fixed250, E):
+    b, ids, s = fixed250
+    b.uniform_E = E
+    b.max_E = E
+    n = b.n_pairs
+    acc, cnt = results(gpu_ctx.filter_magnet(b), n)[SS]
+    check_properties({SS: (acc, cnt)}, E)
+    wa, wc = oracle.magnet_batch(s.reads, s.refs, s.len, E)
+    _sampled(acc, cnt, ids, wa, wc, f"MAGNET E={E}")
+    gpu_ctx.check()
+
+
+@pytest.mark.parametrize("E", [5, 10, 25])
+def test_full_size_verify_survivors(gpu_ctx, fixed250, E):
+    b, ids, s = fixed250
+    b.uniform_E = E
+    b.max_E = E
+    n = b.n_pairs
+    out = gpu_ctx.filter(b, SS)
+    d_sel = gpu_ctx.verify(b, out[SS][0])
+    d_all = gpu_ctx.verify(b)
+    torch.cuda.synchronize()
+    assert torch.equal(d_sel, d_all), "verifying the survivors differs from verifying every pair"
+    d = paf.counts_u16(d_all).cpu().numpy().astype(np.uint16)
+    assert np.all(d <= E + 1)
+    want = oracle.banded_batch(s.reads, s.refs, s.len, np.full(s.n, E))
+    bad = np.nonzero(d[ids.astype(np.int64)] != want)[0]
+    assert bad.size == 0, f"E={E}: {bad.size} sampled distances differ from the oracle"
+    # A pair within E edits always survives SneakySnake.
+    acc = paf.accept_bits_to_bool(out[SS][0], n).cpu().numpy()
+    assert np.all(acc[d <= E])
+    gpu_ctx.check()
