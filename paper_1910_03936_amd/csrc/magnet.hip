@@ -15,7 +15,8 @@
 // cover m - E columns), and with E = 0 the answer decides the pair; the
 // others are flagged.  A stable counting sort of the flags (the bucketing
 // kernels) lists the flagged pairs first, and the second kernel's waves take
-// that list 64 pairs at a time through the extractions;
+// that list 64 pairs at a time through the extractions, each lane holding its
+// pair's words and excluded columns in registers;
 // a pair is also rejected as soon as the runs still to come, none longer than
 // the last one, cannot reach m - E columns.
 //
@@ -31,12 +32,6 @@
 namespace paf {
 
 namespace {
-
-// LDS of one wave, in 8-byte words: the excluded-column rows (4 bytes per
-// word and lane) and the best-run cache (4 bytes per diagonal and lane).
-__host__ __device__ constexpr size_t magnet_wave_words(uint32_t wmax, int D) {
-    return ((size_t)wmax * kLdsRow + 1) / 2 + (size_t)D * 32;
-}
 
 // Longest run of ones inside one word x != ~0 and its lowest start.
 __device__ __forceinline__ void word_longest(uint32_t x, uint32_t& L, uint32_t& s) {
@@ -102,24 +97,6 @@ __device__ bool magnet_first_test(const uint64_t* rd, const uint64_t* rf, int W,
     return found;
 }
 
-// Columns [a, b) leave the search space.
-__device__ __forceinline__ void magnet_exclude(uint32_t* goneL, int lane, uint32_t wmax, uint32_t a, uint32_t b) {
-    for (uint32_t k = 0; k < wmax; ++k) {
-        const uint32_t lo = 32u * k;
-        const uint32_t x0 = a > lo ? min(a - lo, 32u) : 0u;
-        const uint32_t x1 = b > lo ? min(b - lo, 32u) : 0u;
-        // bits [x0, x1) of the word
-        const uint32_t hi_mask = x1 >= 32u ? ~0u : ((1u << x1) - 1u);
-        const uint32_t lo_mask = x0 >= 32u ? ~0u : ((1u << x0) - 1u);
-        goneL[k * kLdsRow + lane] |= hi_mask & ~lo_mask;
-    }
-}
-
-__device__ __forceinline__ void magnet_encapsulate(uint32_t* goneL, int lane, uint32_t wmax, uint32_t m,
-                                                   uint32_t s, uint32_t L) {
-    magnet_exclude(goneL, lane, wmax, s > 0 ? s - 1u : 0u, min(s + L + 1u, m));
-}
-
 // A diagonal's best run (the longest, then the earliest) packed as L << 16 | s.
 __device__ __forceinline__ uint32_t run_pack(uint32_t L, uint32_t s) { return (L << 16) | s; }
 
@@ -149,32 +126,61 @@ __device__ __forceinline__ void diag_word(uint32_t x, uint32_t k, uint32_t& carr
     carry = x == 0u ? 0u : (uint32_t)__builtin_clz(~x);
 }
 
-// The best run of one diagonal d (chosen at run time, |d| <= 31) of the pair
-// whose W words start at rd and rf.
-__device__ uint32_t scan_one(const uint64_t* rd, const uint64_t* rf, const uint32_t* goneL, int lane, uint32_t W,
-                             int m, int d) {
-    uint32_t carry = 0, bL = 0, bS = 0;
-    const uint32_t sp = (uint32_t)d, sn = (uint32_t)(32 + d);
-    for (uint32_t k = 0; k < W; ++k) {
-        const WindowWords q = window_words_direct(rd, rf, (int)k, (int)W, m);
-        uint32_t lo, hi, v;
-        if (d > 0) {
-            lo = funnel(q.nlo, q.clo, sp);
-            hi = funnel(q.nhi, q.chi, sp);
-            v = funnel(q.vn, q.vc, sp);
-        } else if (d < 0) {
-            lo = funnel(q.clo, q.plo, sn);
-            hi = funnel(q.chi, q.phi, sn);
-            v = funnel(q.vc, q.vp, sn);
-        } else {
-            lo = q.clo;
-            hi = q.chi;
-            v = q.vc;
-        }
-        const uint32_t x = ~((lo ^ q.flo) | (hi ^ q.fhi) | v | q.vc | goneL[k * kLdsRow + lane]);
-        diag_word(x, k, carry, bL, bS);
+// The lane's pair held in registers: WM words of each sequence (zero past its
+// W words) and the mask of columns that left the search space.
+template <int WM>
+struct PairRegs {
+    uint64_t rd[WM], rf[WM];
+    uint32_t gone[WM];
+    uint32_t m, W;
+};
+
+// Columns [a, b) leave the search space.
+template <int WM>
+__device__ __forceinline__ void exclude_cols(PairRegs<WM>& r, uint32_t a, uint32_t b) {
+#pragma unroll
+    for (int k = 0; k < WM; ++k) {
+        const uint32_t lo = 32u * k;
+        const uint32_t x0 = a > lo ? min(a - lo, 32u) : 0u;
+        const uint32_t x1 = b > lo ? min(b - lo, 32u) : 0u;
+        const uint32_t hi_mask = x1 >= 32u ? ~0u : ((1u << x1) - 1u);
+        const uint32_t lo_mask = x0 >= 32u ? ~0u : ((1u << x0) - 1u);
+        r.gone[k] |= hi_mask & ~lo_mask;
     }
-    diag_offer(bL, bS, carry, 32u * W - carry);
+}
+
+// The best run of one diagonal d (chosen at run time, |d| <= 31).
+template <int WM>
+__device__ uint32_t scan_one(const PairRegs<WM>& r, int d) {
+    uint32_t carry = 0, bL = 0, bS = 0;
+    const uint32_t sp = (uint32_t)d & 31u, sn = (uint32_t)(32 + d) & 31u;
+    const int m = (int)r.m;
+#pragma unroll
+    for (int k = 0; k < WM; ++k) {
+        if ((uint32_t)k < r.W) {
+            const uint64_t p = k > 0 ? r.rd[k - 1] : 0ull;
+            const uint64_t c = r.rd[k];
+            const uint64_t n = k + 1 < WM ? r.rd[k + 1] : 0ull;
+            const uint32_t vp = vacant_word(k - 1, m), vc = vacant_word(k, m), vn = vacant_word(k + 1, m);
+            uint32_t lo, hi, v;
+            if (d > 0) {
+                lo = funnel((uint32_t)n, (uint32_t)c, sp);
+                hi = funnel((uint32_t)(n >> 32), (uint32_t)(c >> 32), sp);
+                v = funnel(vn, vc, sp);
+            } else if (d < 0) {
+                lo = funnel((uint32_t)c, (uint32_t)p, sn);
+                hi = funnel((uint32_t)(c >> 32), (uint32_t)(p >> 32), sn);
+                v = funnel(vc, vp, sn);
+            } else {
+                lo = (uint32_t)c;
+                hi = (uint32_t)(c >> 32);
+                v = vc;
+            }
+            const uint32_t x = ~((lo ^ (uint32_t)r.rf[k]) | (hi ^ (uint32_t)(r.rf[k] >> 32)) | v | vc | r.gone[k]);
+            diag_word(x, (uint32_t)k, carry, bL, bS);
+        }
+    }
+    diag_offer(bL, bS, carry, 32u * r.W - carry);
     return run_pack(bL, bS);
 }
 
@@ -200,47 +206,44 @@ __global__ void __launch_bounds__(256) magnet_test_kernel(FilterParams P, uint8_
     flag[s.id] = found && s.E > 0 ? 0 : 1;
 }
 
-template <int EMAX>
+template <int EMAX, int WM>
 __global__ void __launch_bounds__(256) magnet_kernel(FilterParams P, const uint32_t* order, const uint32_t* count) {
     constexpr int D = 2 * EMAX + 1;
-    extern __shared__ uint64_t lds[];
+    extern __shared__ uint32_t lds32[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const uint32_t wmax = P.wmax;
-    const size_t per_wave = magnet_wave_words(wmax, D);
-    uint32_t* goneL = reinterpret_cast<uint32_t*>(lds + (size_t)wave * per_wave);
-    uint32_t* cache = goneL + (size_t)wmax * kLdsRow;
+    uint32_t* cache = lds32 + (size_t)wave * D * 64;
     const uint32_t n_sel = *count;
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
 
-    // The extractions of the flagged pairs, 64 at a time.
-    // Each diagonal's best run is kept in `cache`; after an extraction only
-    // the diagonals whose best run meets the excluded columns are searched
-    // again (the others keep their best: excluding columns only shortens
-    // runs).
+    // The extractions of the flagged pairs, 64 at a time, each lane's pair
+    // in its registers.  Each diagonal's best run is kept in `cache`; after
+    // an extraction only the diagonals whose best run meets the excluded
+    // columns are searched again (the others keep their best: excluding
+    // columns only shortens runs).
     for (uint32_t h = (blockIdx.x * (blockDim.x >> 6) + wave) * 64u; h < n_sel; h += waves * 64u) {
         const uint32_t j = h + (uint32_t)lane;
         const bool valid = j < n_sel;
-        PairSlot s;
-        s.valid = s.in_batch = valid;
-        s.slot = s.id = valid ? order[j] : 0u;
-        s.m = valid ? (P.len ? P.len[s.id] : P.uniform_len) : 0u;
-        s.E = valid ? (P.E ? P.E[s.id] : P.uniform_E) : 0u;
-        s.W = (s.m + 31) >> 5;
-        const uint64_t off = !valid ? 0 : P.word_offset ? P.word_offset[s.id] : s.id * (uint64_t)P.stride_words;
-        // The pair's words are read straight from memory (they stay in the
-        // caches across its extractions).
-        const uint64_t* rd = P.reads + off;
-        const uint64_t* rf = P.refs + off;
-        for (uint32_t k = 0; k < wmax; ++k) goneL[k * kLdsRow + lane] = 0u;
+        const uint64_t id = valid ? order[j] : 0u;
+        PairRegs<WM> r;
+        r.m = valid ? (P.len ? P.len[id] : P.uniform_len) : 0u;
+        const uint32_t E = valid ? (P.E ? P.E[id] : P.uniform_E) : 0u;
+        r.W = (r.m + 31) >> 5;
+        const uint64_t off = !valid ? 0 : P.word_offset ? P.word_offset[id] : id * (uint64_t)P.stride_words;
+#pragma unroll
+        for (int k = 0; k < WM; ++k) {
+            r.rd[k] = (uint32_t)k < r.W ? P.reads[off + k] : 0ull;
+            r.rf[k] = (uint32_t)k < r.W ? P.refs[off + k] : 0ull;
+            r.gone[k] = 0u;
+        }
         for (int i = 0; i < D; ++i) {
             const int d = i - EMAX;
-            const bool on = valid && (d < 0 ? -d : d) <= (int)s.E;
-            cache[i * 64 + lane] = on ? scan_one(rd, rf, goneL, lane, s.W, (int)s.m, d) : 0u;
+            const bool on = valid && (d < 0 ? -d : d) <= (int)E;
+            cache[i * 64 + lane] = on ? scan_one<WM>(r, d) : 0u;
         }
         uint32_t covered = 0;
-        bool act = valid, rejected = false;
-        for (uint32_t it = 1; act; ++it) {
+        bool rejected = false;
+        for (uint32_t it = 1; valid; ++it) {
             // The best run over all diagonals (ties: earliest start, then
             // the first diagonal).
             uint32_t bL = 0, bS = 0;
@@ -250,14 +253,14 @@ __global__ void __launch_bounds__(256) magnet_kernel(FilterParams P, const uint3
             }
             if (bL == 0) break;
             covered += bL;
-            const uint32_t a = bS > 0 ? bS - 1u : 0u, b = min(bS + bL + 1u, s.m);
-            magnet_exclude(goneL, lane, wmax, a, b);
+            const uint32_t a = bS > 0 ? bS - 1u : 0u, b = min(bS + bL + 1u, r.m);
+            exclude_cols<WM>(r, a, b);
             // The E + 1 - it runs still to come are no longer than this one.
-            if (covered + (s.E + 1u - it) * bL + s.E < s.m) {
+            if (covered + (E + 1u - it) * bL + E < r.m) {
                 rejected = true;
                 break;
             }
-            if (it > s.E || covered >= s.m) break;
+            if (it > E || covered >= r.m) break;
             uint64_t dirty = 0;
             for (int i = 0; i < D; ++i) {
                 const uint32_t v = cache[i * 64 + lane];
@@ -267,11 +270,10 @@ __global__ void __launch_bounds__(256) magnet_kernel(FilterParams P, const uint3
             while (dirty) {
                 const int i = __builtin_ctzll(dirty);
                 dirty &= dirty - 1;
-                cache[i * 64 + lane] = scan_one(rd, rf, goneL, lane, s.W, (int)s.m, i - EMAX);
+                cache[i * 64 + lane] = scan_one<WM>(r, i - EMAX);
             }
         }
-        if (valid) P.cnt[0][s.id] = (uint16_t)(rejected ? s.E + 1u : min(s.m - covered, s.E + 1u));
-        wave_lds_sync();
+        if (valid) P.cnt[0][id] = (uint16_t)(rejected ? E + 1u : min(r.m - covered, E + 1u));
     }
 }
 
@@ -288,10 +290,11 @@ const void* magnet_test_kernel_for(int emax) {
     }
 }
 
+template <int WM>
 const void* magnet_kernel_for(int emax) {
     switch (emax) {
 #define PAF_CASE(X) \
-    case X: return reinterpret_cast<const void*>(&magnet_kernel<X>);
+    case X: return reinterpret_cast<const void*>(&magnet_kernel<X, WM>);
         PAF_CASE(0) PAF_CASE(1) PAF_CASE(2) PAF_CASE(3) PAF_CASE(4) PAF_CASE(5) PAF_CASE(6)
         PAF_CASE(7) PAF_CASE(8) PAF_CASE(10) PAF_CASE(12) PAF_CASE(15) PAF_CASE(20) PAF_CASE(25)
         PAF_CASE(31)
@@ -306,7 +309,9 @@ hipError_t launch_magnet(const FilterParams& p, int emax, uint8_t* flag, uint32_
                          uint32_t* hist, int num_cus, hipStream_t s) {
     const bool general = p.len || p.E || p.word_offset;
     const void* kt = general ? magnet_test_kernel_for<true>(emax) : magnet_test_kernel_for<false>(emax);
-    const void* k = magnet_kernel_for(emax);
+    // Pairs of up to 256 bases keep 8 words per sequence in registers, longer
+    // ones 16.
+    const void* k = p.wmax <= 8 ? magnet_kernel_for<8>(emax) : magnet_kernel_for<16>(emax);
     if (!kt || !k) return hipErrorInvalidValue;
     FilterParams arg = p;
     const uint32_t waves = 4;
@@ -320,7 +325,7 @@ hipError_t launch_magnet(const FilterParams& p, int emax, uint8_t* flag, uint32_
     hipError_t e = launch_bucket_sort(flag, p.n_pairs, counts, order, hist, s);
     if (e != hipSuccess) return e;
     // A grid that fills the chip; its waves stride over the list.
-    const size_t lds = waves * magnet_wave_words(p.wmax, 2 * emax + 1) * sizeof(uint64_t);
+    const size_t lds = (size_t)waves * (2 * emax + 1) * 64 * sizeof(uint32_t);
     if (lds > 65536) {
         e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
