@@ -433,13 +433,17 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                     // snake's column lives in a one-hot word b: a probe from
                     // b gives the run [s, s + L) as above, and runs + b is
                     // the bit of the obstacle at s + L (zero when a pipe runs
-                    // through the window's end).  An obstacle inside the pair
-                    // costs one edit, and the next probe starts one column
-                    // after it.  The lane probes while b is a column of the
-                    // pair and e <= E.
+                    // through the window's end); the next probe starts one
+                    // column after it, (runs + b) << 1.  The lane probes
+                    // while b is a column of the pair (so the last probe's
+                    // obstacle was inside the pair and cost an edit) and the
+                    // edits stay within E: every probe but the last costs one
+                    // edit, so the loop only counts probes and the last one
+                    // is settled after it.
                     const uint32_t inpair = m >= w0 + 32u ? ~0u : (1u << (m - w0)) - 1u;
                     uint32_t b = act ? 1u : 0u, runs = 0;
-                    while ((b & inpair) != 0u && e <= E) {
+                    int32_t budget = (int32_t)E - (int32_t)e;
+                    while ((b & inpair) != 0u && budget >= 0) {
                         uint32_t r0 = 0, r1 = 0;
 #pragma unroll
                         for (int d = 0; d < D; d += 2) {
@@ -447,15 +451,19 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                             if (d + 1 < D) r1 = or_andn(r1, M[d + 1], M[d + 1] + b);
                         }
                         runs = r0 | r1;
-                        const uint32_t ob = runs + b;
-                        e += min(ob & inpair, 1u);
-                        b = ob << 1;
+                        b = (runs + b) << 1;
+                        --budget;
                     }
                     if (live) {
+                        const uint32_t probes = (uint32_t)((int32_t)E - (int32_t)e - budget);
+                        clear = runs >> 31;
+                        // The last probe's obstacle (none when its pipe ran
+                        // through the window's end; bit 31 when b wrapped to 0).
+                        const uint32_t ob = clear ? 0u : (b != 0u ? b >> 1 : 0x80000000u);
+                        e += probes - (probes != 0u && (ob & inpair) == 0u ? 1u : 0u);
                         // The column reached: past the pair's end inside the
                         // window, or the next window's first column.
                         c = b != 0u ? w0 + (uint32_t)__builtin_ctz(b) : w0 + 32u;
-                        clear = runs >> 31;
                         // The last probe's start, for the dead-diagonal mask
                         // of a pipe running on (its run is [s, 32)).
                         bs = runs & (0u - runs);
