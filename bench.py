@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_GIPS = 256 * 4 * 2.4 / 4   # wave64 VALU instructions per ns: 614.4 G/s
 
 
 def log(msg: str):
@@ -213,10 +214,20 @@ def main():
     def roof(kern_ms, bytes_pair, kernel, key):
         achieved = n * bytes_pair / (kern_ms / 1e3) / 1e9
         tr = traffic_record(os.path.join(ROOT, "paper_1910_03936_amd", "csrc", "filter.hip"), key)
-        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if tr is None else tr["bytes_per_launch"] * n / tr["n_pairs"],
-                "kernel": kernel, "kernel_ms": round(kern_ms, 4), "alg_bytes_per_pair": round(bytes_pair, 3)}
+        r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(achieved / HBM_PEAK_GBS, 4),
+             "traffic": None if tr is None else tr["bytes_per_launch"] * n / tr["n_pairs"],
+             "kernel": kernel, "kernel_ms": round(kern_ms, 4), "alg_bytes_per_pair": round(bytes_pair, 3)}
+        if tr is not None and "valu_insts_per_launch" in tr:
+            # The filter is integer bit work: what it is bound by in fact is
+            # the VALU issue rate (256 CUs x 4 SIMDs, one wave64 instruction
+            # per 4 cycles each, 2.4 GHz).  Instructions per launch from the
+            # profiled counters (same kernel source), over this run's time.
+            ips = tr["valu_insts_per_launch"] * n / tr["n_pairs"] / (kern_ms / 1e3)
+            r["valu_issue"] = {"achieved": round(ips / 1e9, 1), "peak": VALU_PEAK_GIPS, "unit": "G wave-instr/s",
+                               "frac": round(ips / 1e9 / VALU_PEAK_GIPS, 4),
+                               "lane_util": round(tr.get("valu_lane_util", 0.0), 3)}
+        return r
 
     plain = {"value": plain_value, "ms_per_step": plain_ms,
              "roofline": roof(plain_kern_ms, plain_bytes_pair,
