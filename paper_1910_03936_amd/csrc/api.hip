@@ -245,9 +245,9 @@ paf_status ensure_bucket_ws(paf_ctx* ctx, uint64_t n) {
 
 // Launch layout: the forced one, else the autotuned one for this class, else
 // the default (work queue for the persistent entry point; for orders given
-// by a permutation, a full grid of one-wave blocks, compacting 8-tile chunks
-// for SneakySnake alone, where measured dispatch by the hardware beat the
-// queue).
+// by a permutation, a full grid of two-wave blocks, compacting 6-tile chunks
+// and two-window passes for SneakySnake alone, where measured dispatch by
+// the hardware beat the queue).
 paf_layout layout_for(paf_ctx* ctx, const FilterParams& p, int emax, bool queue_default = true) {
     if (ctx->layout_forced) return ctx->forced;
     auto it = ctx->tuned.find(std::make_tuple((int)p.wmax, emax, p.filters));
@@ -707,7 +707,7 @@ paf_status paf_cost_levels(paf_ctx* ctx, const paf_batch* batch, uint8_t* key, v
 }
 
 // Layout of the keyed compacting launch: the forced or tuned one if it
-// compacts, else one-wave blocks with 8-tile chunks.
+// compacts, else two-wave blocks with 6-tile chunks and two-window passes.
 paf_layout keyed_layout(paf_ctx* ctx, const FilterParams& p, int emax) {
     paf_layout L = layout_for(ctx, p, emax, false);
     if (L.chunk_tiles == 0) L = paf_layout{1u, 2u, 0u, 1u, 6u, 2u, 2u};
