@@ -57,7 +57,7 @@ __device__ __forceinline__ void word_longest(uint32_t x, uint32_t& L, uint32_t& 
 // need - 1, leaves the starts of runs of need cells).
 template <int EMAX, int I = 0>
 __device__ __forceinline__ void magnet_has_run(const WindowWords& q, uint32_t blocked, int E, uint32_t need,
-                                               const uint32_t* sh, uint32_t* carry, bool& found) {
+                                               const uint32_t* sh, uint32_t* carry, uint32_t& found) {
     if constexpr (I < 2 * EMAX + 1) {
         constexpr int d = I - EMAX;
         const bool on = (d < 0 ? -d : d) <= E;
@@ -66,14 +66,16 @@ __device__ __forceinline__ void magnet_has_run(const WindowWords& q, uint32_t bl
         uint32_t r = x;
 #pragma unroll
         for (int j = 0; j < 6; ++j) r &= r >> sh[j];
-        found = found || carry[I] + t >= need || (need <= 32u && r != 0u);
+        // (bitwise, so that no branch is taken per diagonal)
+        found |= (uint32_t)(carry[I] + t >= need) | (uint32_t)(r != 0u);
         carry[I] = x == ~0u ? carry[I] + 32u : (x == 0u ? 0u : (uint32_t)__builtin_clz(~x));
         magnet_has_run<EMAX, I + 1>(q, blocked, E, need, sh, carry, found);
     }
 }
 
 template <int EMAX>
-__device__ bool magnet_first_test(const uint64_t* rd, const uint64_t* rf, int W, int m, int E, uint32_t need) {
+__device__ __forceinline__ bool magnet_first_test(const uint64_t* rd, const uint64_t* rf, int W, int m, int E,
+                                                  uint32_t need) {
     constexpr int D = 2 * EMAX + 1;
     uint32_t carry[D];
 #pragma unroll
@@ -87,14 +89,14 @@ __device__ bool magnet_first_test(const uint64_t* rd, const uint64_t* rf, int W,
         sh[j] = min(len, min(want, 31u));
         len += sh[j];
     }
-    bool found = need == 0u;
+    uint32_t found = need == 0u ? 1u : 0u;
     for (int k = 0; k < W; ++k) {
         const WindowWords q = window_words_direct(rd, rf, k, W, m);
         magnet_has_run<EMAX>(q, q.vc, E, need, sh, carry, found);
     }
 #pragma unroll
-    for (int i = 0; i < D; ++i) found = found || carry[i] >= need;
-    return found;
+    for (int i = 0; i < D; ++i) found |= (uint32_t)(carry[i] >= need);
+    return found != 0u;
 }
 
 // A diagonal's best run (the longest, then the earliest) packed as L << 16 | s.
