@@ -70,17 +70,22 @@ __device__ uint32_t band_distance(const uint64_t* rdL, const uint64_t* rfL, int 
         if (F[EMAX] >= m) dist = 0;
         if (F[EMAX] >= m || E == 0) act = false;
     }
-    // Diagonals beyond the pair's threshold or length stay unreachable.
+    // Diagonals beyond the pair's threshold or length stay unreachable.  A
+    // path on diagonal d after k edits needs |d| more to end on diagonal 0,
+    // so round k only extends the diagonals with k + |d| <= E: the others
+    // cannot lie on an alignment within E edits (and the rounds after k
+    // only read diagonals that round k kept).
     const int lim = min(E, m);
     for (int k = 1; wave_any(act); ++k) {
         if (act) {
             int left = kNeg;   // F_{k-1}[d-1]
+            const int reach = min(k, min(lim, E - k));
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 const int d = i - EMAX;
                 const int old = F[i];
                 const int ad = d < 0 ? -d : d;
-                if (ad <= k && ad <= lim) {
+                if (ad <= reach) {
                     int x = old + 1;
                     if (i + 1 < D) x = max(x, F[i + 1] + 1);
                     x = max(x, left);
