@@ -16,9 +16,9 @@
 // others are flagged.  A stable counting sort of the flags (the bucketing
 // kernels) lists the flagged pairs first, and the second kernel's waves take
 // that list 64 pairs at a time through the extractions, each lane holding its
-// pair's words and excluded columns in registers;
-// a pair is also rejected as soon as the runs still to come, none longer than
-// the last one, cannot reach m - E columns.
+// pair's words and excluded columns in registers; a pair is also rejected as
+// soon as the runs still to come, none longer than the last one, cannot reach
+// m - E columns.
 //
 // A diagonal's longest run is found word by word: the run that enters a
 // 32-column word from below ends at the word's first blocked column (a
@@ -54,7 +54,7 @@ __device__ __forceinline__ void word_longest(uint32_t x, uint32_t& L, uint32_t& 
 // Whether some diagonal has a run of at least `need` free cells: per word,
 // the run entering from below (carry + trailing free cells) and the runs
 // inside the word (x AND-ed with itself shifted by sh[0..5], which add up to
-// need - 1, leaves the starts of runs of need cells).
+// need - 1, leaves the starts of runs of need cells; none when need > 32).
 template <int EMAX, int I = 0>
 __device__ __forceinline__ void magnet_has_run(const WindowWords& q, uint32_t blocked, int E, uint32_t need,
                                                const uint32_t* sh, uint32_t* carry, uint32_t& found) {
