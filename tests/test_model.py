@@ -391,3 +391,37 @@ def test_filter_keyed_any_key(gpu_ctx):
             torch.cuda.synchronize()
             assert torch.equal(plain[SS][0], got[SS][0]) and torch.equal(plain[SS][1], got[SS][1])
     gpu_ctx.check()
+
+
+def _wave_spread(cost: np.ndarray, order: np.ndarray) -> float:
+    """Sum over consecutive groups of 64 pairs (one wave) of the largest minus
+    the smallest true cost: what lanes of one wave wait for each other."""
+    c = cost[order]
+    n = (c.size // 64) * 64
+    g = c[:n].reshape(-1, 64)
+    return float((g.max(1) - g.min(1)).sum())
+
+
+@gpu
+def test_trained_model_groups_pairs_of_like_cost(gpu_ctx):
+    """What the trained network gains over the method without it: ordering
+    held-out pairs by its prediction puts pairs of like SneakySnake cost (the
+    obstacle count of the whole maze, the label) into the same waves, which
+    input order and an untrained network do not."""
+    from paper_1910_03936_amd import costmodel
+    from gpu_util import to_device
+    w = pairgen.UNEVEN_MIX.with_seed(123)
+    p = pairgen.generate(w, 0, 16384)
+    b = to_device(p, gpu_ctx, per_pair=True, offsets=True)
+    cost = oracle.filter_batch(p.reads, p.refs, p.len, costmodel.LABEL_E)[oracle.SNEAKYSNAKE][1].astype(np.float64)
+    gpu_ctx.mlp_set_params(pairgen.init_mlp_params())
+    untrained = gpu_ctx.mlp_predict(b).cpu().numpy()
+    costmodel.train(gpu_ctx, pairgen.UNEVEN_MIX, n=200_000, epochs=3, batch=4096, lr=2e-3)
+    trained = gpu_ctx.mlp_predict(b).cpu().numpy()
+    plain = _wave_spread(cost, np.arange(p.n))
+    best = _wave_spread(cost, np.argsort(cost, kind="stable"))
+    by_untrained = _wave_spread(cost, np.argsort(untrained, kind="stable"))
+    by_trained = _wave_spread(cost, np.argsort(trained, kind="stable"))
+    assert by_trained < 0.5 * plain, (by_trained, plain)
+    assert by_trained < 0.7 * by_untrained, (by_trained, by_untrained)
+    assert best <= by_trained

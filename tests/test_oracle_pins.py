@@ -560,3 +560,18 @@ def test_fpga_tile_enough_replications_is_partitioned_maze():
             a, c = oracle.sneakysnake_fpga_batch(p.reads, p.refs, p.len, E, t, t)
             a2, c2 = oracle.sneakysnake_t_batch(p.reads, p.refs, p.len, E, t)
             assert np.array_equal(a, a2) and np.array_equal(c, c2)
+
+
+def test_magnet_first_run_test_is_implied_by_the_final_one():
+    # Sec. 7.2 rejects at once when the longest run is shorter than
+    # ceil((m - E) / (E + 1)); the E + 1 runs found later are no longer, so
+    # such a pair is rejected by the final test anyway (count E + 1).
+    p = pairgen.generate(pairgen.SMALL_100BP, 9, 600)
+    m = 100
+    for E in (2, 5, 9):
+        need = -(-(m - E) // (E + 1))
+        assert need == m // (E + 1)      # the form the GPU test uses
+        for i in range(p.n):
+            acc, cnt, segs = oracle.magnet(p.reads[i], p.refs[i], E, with_segments=True)
+            if segs[0][2] < need:
+                assert not acc and cnt == E + 1
