@@ -14,10 +14,14 @@
 // the pair is rejected (Sec. 7.2's first test: E + 1 runs that short cannot
 // cover m - E columns), and with E = 0 the answer decides the pair; the
 // others are flagged.  A stable counting sort of the flags (the bucketing
-// kernels) lists the flagged pairs first, and the second kernel's waves take
-// that list 64 pairs at a time through the extractions, each lane holding its
-// pair's words and excluded columns in registers; a pair is also rejected as
-// soon as the runs still to come, none longer than the last one, cannot reach
+// kernels) lists the flagged pairs first.  Each wave of the second kernel
+// takes an equal share of that list; each lane holds one pair's words and
+// excluded columns in registers and takes the next pair of the share when
+// its own is done.  Per diagonal it keeps one ordering key in LDS: the best
+// run found by the last scan, or before any scan the diagonal's free-cell
+// count as an upper bound.  A step takes the largest key: an exact one is
+// extracted, a stale one is scanned again.  A pair is also rejected as soon
+// as the runs still to come, none longer than the last one, cannot reach
 // m - E columns.
 //
 // A diagonal's longest run is found word by word: the run that enters a
@@ -99,35 +103,6 @@ __device__ __forceinline__ bool magnet_first_test(const uint64_t* rd, const uint
     return found != 0u;
 }
 
-// A diagonal's best run (the longest, then the earliest) packed as L << 16 | s.
-__device__ __forceinline__ uint32_t run_pack(uint32_t L, uint32_t s) { return (L << 16) | s; }
-
-// Offer the run [s, s + L) of one diagonal to that diagonal's best.
-__device__ __forceinline__ void diag_offer(uint32_t& bL, uint32_t& bS, uint32_t L, uint32_t s) {
-    const bool take = L > bL || (L == bL && L > 0 && s < bS);
-    bL = take ? L : bL;
-    bS = take ? s : bS;
-}
-
-// One word x of a diagonal: the run entering from below ends at the word's
-// first blocked column; runs inside the word are searched when one could
-// beat the diagonal's best; the free cells at the top carry on.
-__device__ __forceinline__ void diag_word(uint32_t x, uint32_t k, uint32_t& carry, uint32_t& bL, uint32_t& bS) {
-    if (x == ~0u) {
-        carry += 32u;
-        return;
-    }
-    const uint32_t t = (uint32_t)__builtin_ctz(~x);
-    diag_offer(bL, bS, carry + t, 32u * k - carry);
-    const uint32_t pc = popc(x);
-    if (pc > bL || (pc == bL && 32u * k < bS)) {
-        uint32_t L, s;
-        word_longest(x, L, s);
-        diag_offer(bL, bS, L, 32u * k + s);
-    }
-    carry = x == 0u ? 0u : (uint32_t)__builtin_clz(~x);
-}
-
 // The lane's pair held in registers: WM words of each sequence (zero past its
 // W words) and the mask of columns that left the search space.
 template <int WM>
@@ -137,53 +112,101 @@ struct PairRegs {
     uint32_t m, W;
 };
 
+// Bits of columns [a, b) that fall in word k.
+__device__ __forceinline__ uint32_t cols_mask(int k, uint32_t a, uint32_t b) {
+    const uint32_t lo = 32u * (uint32_t)k;
+    const uint32_t x0 = a > lo ? min(a - lo, 32u) : 0u;
+    const uint32_t x1 = b > lo ? min(b - lo, 32u) : 0u;
+    const uint32_t hi_mask = x1 >= 32u ? ~0u : ((1u << x1) - 1u);
+    const uint32_t lo_mask = x0 >= 32u ? ~0u : ((1u << x0) - 1u);
+    return hi_mask & ~lo_mask;
+}
+
 // Columns [a, b) leave the search space.
 template <int WM>
 __device__ __forceinline__ void exclude_cols(PairRegs<WM>& r, uint32_t a, uint32_t b) {
 #pragma unroll
-    for (int k = 0; k < WM; ++k) {
-        const uint32_t lo = 32u * k;
-        const uint32_t x0 = a > lo ? min(a - lo, 32u) : 0u;
-        const uint32_t x1 = b > lo ? min(b - lo, 32u) : 0u;
-        const uint32_t hi_mask = x1 >= 32u ? ~0u : ((1u << x1) - 1u);
-        const uint32_t lo_mask = x0 >= 32u ? ~0u : ((1u << x0) - 1u);
-        r.gone[k] |= hi_mask & ~lo_mask;
-    }
+    for (int k = 0; k < WM; ++k) r.gone[k] |= cols_mask(k, a, b);
 }
 
-// The best run of one diagonal d (chosen at run time, |d| <= 31).
+// Whether some column of [a, b) has left the search space.
 template <int WM>
-__device__ uint32_t scan_one(const PairRegs<WM>& r, int d) {
-    uint32_t carry = 0, bL = 0, bS = 0;
-    const uint32_t sp = (uint32_t)d & 31u, sn = (uint32_t)(32 + d) & 31u;
+__device__ __forceinline__ bool meets_gone(const PairRegs<WM>& r, uint32_t a, uint32_t b) {
+    uint32_t hit = 0;
+#pragma unroll
+    for (int k = 0; k < WM; ++k) hit |= r.gone[k] & cols_mask(k, a, b);
+    return hit != 0u;
+}
+
+// Free cells of word k of diagonal d (chosen per lane, |d| <= 31): the read
+// words around k funnel-shifted by d & 31 (those of k and k + 1 for d >= 0,
+// of k - 1 and k otherwise), compared with the reference word; vacant cells
+// and excluded columns are blocked.
+template <int WM>
+__device__ __forceinline__ uint32_t free_word(const PairRegs<WM>& r, int k, bool pos, uint32_t sh) {
     const int m = (int)r.m;
+    const uint64_t p = k > 0 ? r.rd[k - 1] : 0ull;
+    const uint64_t c = r.rd[k];
+    const uint64_t n = k + 1 < WM ? r.rd[k + 1] : 0ull;
+    const uint64_t H = pos ? n : c, L = pos ? c : p;
+    const uint32_t vc = vacant_word(k, m);
+    const uint32_t vh = pos ? vacant_word(k + 1, m) : vc, vl = pos ? vc : vacant_word(k - 1, m);
+    const uint32_t lo = funnel((uint32_t)H, (uint32_t)L, sh);
+    const uint32_t hi = funnel((uint32_t)(H >> 32), (uint32_t)(L >> 32), sh);
+    const uint32_t v = funnel(vh, vl, sh);
+    return ~((lo ^ (uint32_t)r.rf[k]) | (hi ^ (uint32_t)(r.rf[k] >> 32)) | v | vc | r.gone[k]);
+}
+
+// Ordering key of a run of diagonal i: longer first, then the smaller start,
+// then the smaller diagonal index (the order of extraction), so the best run
+// over all diagonals is the largest key.  Bit 0 is set when a scan found the
+// run; a key without it (the diagonal's free-cell count, start 0) is an
+// upper bound.  m <= 512 fits the 10-bit fields.
+__device__ __forceinline__ uint32_t run_key(uint32_t L, uint32_t s) { return (L << 17) | ((1023u - s) << 7); }
+__device__ __forceinline__ uint32_t diag_tag(uint32_t i, uint32_t scanned) { return ((63u - i) << 1) | scanned; }
+__device__ __forceinline__ uint32_t key_len(uint32_t key) { return key >> 17; }
+__device__ __forceinline__ uint32_t key_start(uint32_t key) { return 1023u - ((key >> 7) & 1023u); }
+__device__ __forceinline__ uint32_t key_diag(uint32_t key) { return 63u - ((key >> 1) & 63u); }
+
+// The best run of diagonal i (d = i - emax), word by word: the run entering
+// a word from below ends at its first blocked column; runs inside the word
+// are searched only when its free-cell count could beat the best so far; the
+// free cells at the top carry on.  (A run still open at a word's top is also
+// offered there: it is part of a real run with the same start, which is
+// offered in full later.)
+template <int WM>
+__device__ uint32_t scan_key(const PairRegs<WM>& r, uint32_t i, int emax) {
+    const int d = (int)i - emax;
+    const bool pos = d >= 0;
+    const uint32_t sh = (uint32_t)d & 31u;
+    uint32_t carry = 0, best = 0;
 #pragma unroll
     for (int k = 0; k < WM; ++k) {
         if ((uint32_t)k < r.W) {
-            const uint64_t p = k > 0 ? r.rd[k - 1] : 0ull;
-            const uint64_t c = r.rd[k];
-            const uint64_t n = k + 1 < WM ? r.rd[k + 1] : 0ull;
-            const uint32_t vp = vacant_word(k - 1, m), vc = vacant_word(k, m), vn = vacant_word(k + 1, m);
-            uint32_t lo, hi, v;
-            if (d > 0) {
-                lo = funnel((uint32_t)n, (uint32_t)c, sp);
-                hi = funnel((uint32_t)(n >> 32), (uint32_t)(c >> 32), sp);
-                v = funnel(vn, vc, sp);
-            } else if (d < 0) {
-                lo = funnel((uint32_t)c, (uint32_t)p, sn);
-                hi = funnel((uint32_t)(c >> 32), (uint32_t)(p >> 32), sn);
-                v = funnel(vc, vp, sn);
-            } else {
-                lo = (uint32_t)c;
-                hi = (uint32_t)(c >> 32);
-                v = vc;
+            const uint32_t x = free_word<WM>(r, k, pos, sh);
+            const uint32_t t = x == ~0u ? 32u : (uint32_t)__builtin_ctz(~x);
+            best = max(best, run_key(carry + t, 32u * k - carry));
+            if (x != ~0u && run_key(popc(x), 32u * k) > best) {
+                uint32_t L, s;
+                word_longest(x, L, s);
+                best = max(best, run_key(L, 32u * k + s));
             }
-            const uint32_t x = ~((lo ^ (uint32_t)r.rf[k]) | (hi ^ (uint32_t)(r.rf[k] >> 32)) | v | vc | r.gone[k]);
-            diag_word(x, (uint32_t)k, carry, bL, bS);
+            carry = x == ~0u ? carry + 32u : (uint32_t)__builtin_clz(~x);
         }
     }
-    diag_offer(bL, bS, carry, 32u * r.W - carry);
-    return run_pack(bL, bS);
+    best = max(best, run_key(carry, 32u * r.W - carry));
+    return best | diag_tag(i, 1u);
+}
+
+// The bound key of diagonal i before any scan: its number of free cells.
+template <int WM>
+__device__ uint32_t bound_key(const PairRegs<WM>& r, uint32_t i, int emax) {
+    const int d = (int)i - emax;
+    uint32_t pc = 0;
+#pragma unroll
+    for (int k = 0; k < WM; ++k)
+        if ((uint32_t)k < r.W) pc += popc(free_word<WM>(r, k, d >= 0, (uint32_t)d & 31u));
+    return pc ? run_key(pc, 0u) | diag_tag(i, 0u) : 0u;
 }
 
 // Threshold test of every pair; flag[p] = 0 for the pairs left undecided,
@@ -208,74 +231,97 @@ __global__ void __launch_bounds__(256) magnet_test_kernel(FilterParams P, uint8_
     flag[s.id] = found && s.E > 0 ? 0 : 1;
 }
 
+// Refill a wave's idle lanes once this many are idle (or the wave's share
+// has fewer pairs left).
+constexpr uint32_t kRefillLanes = 16;
+
 template <int EMAX, int WM>
 __global__ void __launch_bounds__(256) magnet_kernel(FilterParams P, const uint32_t* order, const uint32_t* count) {
     constexpr int D = 2 * EMAX + 1;
     extern __shared__ uint32_t lds32[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    uint32_t* cache = lds32 + (size_t)wave * D * 64;
-    const uint32_t n_sel = *count;
-    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    uint32_t* key = lds32 + (size_t)wave * D * 64;
+    const uint64_t n_sel = *count;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    // This wave's share of the flagged list.
+    uint64_t next = n_sel * w / waves;
+    const uint64_t end = n_sel * (w + 1) / waves;
 
-    // The extractions of the flagged pairs, 64 at a time, each lane's pair
-    // in its registers.  Each diagonal's best run is kept in `cache`; after
-    // an extraction only the diagonals whose best run meets the excluded
-    // columns are searched again (the others keep their best: excluding
-    // columns only shortens runs).
-    for (uint32_t h = (blockIdx.x * (blockDim.x >> 6) + wave) * 64u; h < n_sel; h += waves * 64u) {
-        const uint32_t j = h + (uint32_t)lane;
-        const bool valid = j < n_sel;
-        const uint64_t id = valid ? order[j] : 0u;
-        PairRegs<WM> r;
-        r.m = valid ? (P.len ? P.len[id] : P.uniform_len) : 0u;
-        const uint32_t E = valid ? (P.E ? P.E[id] : P.uniform_E) : 0u;
-        r.W = (r.m + 31) >> 5;
-        const uint64_t off = !valid ? 0 : P.word_offset ? P.word_offset[id] : id * (uint64_t)P.stride_words;
+    // Each lane runs its own pair and takes a new one when it is done, so a
+    // wave waits for no pair.  A step selects the largest key of the lane's
+    // diagonals.  A key from a scan whose run still avoids the excluded
+    // columns is exact and is extracted; otherwise (a bound, or a run that an
+    // exclusion has cut) the diagonal is scanned again.  Excluding columns
+    // only shortens runs, so a stale key is never below the exact one and the
+    // largest exact key is the true best.
+    PairRegs<WM> r;
+    r.m = 0;
+    r.W = 0;
 #pragma unroll
-        for (int k = 0; k < WM; ++k) {
-            r.rd[k] = (uint32_t)k < r.W ? P.reads[off + k] : 0ull;
-            r.rf[k] = (uint32_t)k < r.W ? P.refs[off + k] : 0ull;
-            r.gone[k] = 0u;
+    for (int k = 0; k < WM; ++k) {
+        r.rd[k] = r.rf[k] = 0ull;
+        r.gone[k] = 0u;
+    }
+    uint64_t id = 0;
+    uint32_t E = 0, covered = 0, it = 0;
+    bool busy = false;
+    for (;;) {
+        const uint64_t idle = __ballot(!busy);
+        const uint32_t n_idle = (uint32_t)__builtin_popcountll(idle);
+        const uint64_t left = end - next;
+        if (left == 0 && n_idle == 64u) break;
+        if (left != 0 && n_idle >= min<uint64_t>(kRefillLanes, left)) {
+            const uint32_t rank =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+            if (!busy && rank < left) {
+                id = order[next + rank];
+                r.m = P.len ? P.len[id] : P.uniform_len;
+                E = P.E ? P.E[id] : P.uniform_E;
+                r.W = (r.m + 31) >> 5;
+                const uint64_t off = P.word_offset ? P.word_offset[id] : id * (uint64_t)P.stride_words;
+#pragma unroll
+                for (int k = 0; k < WM; ++k) {
+                    r.rd[k] = (uint32_t)k < r.W ? P.reads[off + k] : 0ull;
+                    r.rf[k] = (uint32_t)k < r.W ? P.refs[off + k] : 0ull;
+                    r.gone[k] = 0u;
+                }
+                covered = 0;
+                it = 0;
+                for (int i = 0; i < D; ++i) {
+                    const int d = i - EMAX;
+                    key[i * 64 + lane] = (d < 0 ? -d : d) <= (int)E ? bound_key<WM>(r, (uint32_t)i, EMAX) : 0u;
+                }
+                busy = true;
+            }
+            next += min<uint64_t>(n_idle, left);
         }
-        for (int i = 0; i < D; ++i) {
-            const int d = i - EMAX;
-            const bool on = valid && (d < 0 ? -d : d) <= (int)E;
-            cache[i * 64 + lane] = on ? scan_one<WM>(r, d) : 0u;
-        }
-        uint32_t covered = 0;
-        bool rejected = false;
-        for (uint32_t it = 1; valid; ++it) {
-            // The best run over all diagonals (ties: earliest start, then
-            // the first diagonal).
-            uint32_t bL = 0, bS = 0;
-            for (int i = 0; i < D; ++i) {
-                const uint32_t v = cache[i * 64 + lane];
-                diag_offer(bL, bS, v >> 16, v & 0xFFFFu);
+        if (busy) {
+            uint32_t best = 0;
+            for (int i = 0; i < D; ++i) best = max(best, key[i * 64 + lane]);
+            const uint32_t L = key_len(best);
+            bool done = L == 0u, rejected = false;
+            if (!done) {
+                const uint32_t s = key_start(best), i = key_diag(best);
+                if ((best & 1u) == 0u || meets_gone<WM>(r, s, s + L)) {
+                    key[i * 64 + lane] = scan_key<WM>(r, i, EMAX);
+                } else {
+                    // Extraction: the run and one column on each side leave
+                    // the search space.
+                    ++it;
+                    covered += L;
+                    exclude_cols<WM>(r, s > 0 ? s - 1u : 0u, min(s + L + 1u, r.m));
+                    // The E + 1 - it runs still to come are no longer than this one.
+                    rejected = covered + (E + 1u - it) * L + E < r.m;
+                    done = rejected || it > E || covered >= r.m;
+                }
             }
-            if (bL == 0) break;
-            covered += bL;
-            const uint32_t a = bS > 0 ? bS - 1u : 0u, b = min(bS + bL + 1u, r.m);
-            exclude_cols<WM>(r, a, b);
-            // The E + 1 - it runs still to come are no longer than this one.
-            if (covered + (E + 1u - it) * bL + E < r.m) {
-                rejected = true;
-                break;
-            }
-            if (it > E || covered >= r.m) break;
-            uint64_t dirty = 0;
-            for (int i = 0; i < D; ++i) {
-                const uint32_t v = cache[i * 64 + lane];
-                const uint32_t L = v >> 16, st = v & 0xFFFFu;
-                if (L > 0 && st < b && st + L > a) dirty |= 1ull << i;
-            }
-            while (dirty) {
-                const int i = __builtin_ctzll(dirty);
-                dirty &= dirty - 1;
-                cache[i * 64 + lane] = scan_one<WM>(r, i - EMAX);
+            if (done) {
+                P.cnt[0][id] = (uint16_t)(rejected ? E + 1u : min(r.m - covered, E + 1u));
+                busy = false;
             }
         }
-        if (valid) P.cnt[0][id] = (uint16_t)(rejected ? E + 1u : min(r.m - covered, E + 1u));
     }
 }
 
@@ -326,7 +372,7 @@ hipError_t launch_magnet(const FilterParams& p, int emax, uint8_t* flag, uint32_
     // Undecided pairs first (flag 0), in pair order.
     hipError_t e = launch_bucket_sort(flag, p.n_pairs, counts, order, hist, s);
     if (e != hipSuccess) return e;
-    // A grid that fills the chip; its waves stride over the list.
+    // A grid that fills the chip; each wave takes an equal share of the list.
     const size_t lds = (size_t)waves * (2 * emax + 1) * 64 * sizeof(uint32_t);
     if (lds > 65536) {
         e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
