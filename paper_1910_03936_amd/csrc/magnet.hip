@@ -18,9 +18,9 @@
 // takes an equal share of that list; each lane holds one pair's words and
 // excluded columns in registers and takes the next pair of the share when
 // its own is done.  Per diagonal it keeps one ordering key in LDS: the best
-// run found by the last scan, or before any scan the diagonal's free-cell
-// count as an upper bound.  A step takes the largest key: an exact one is
-// extracted, a stale one is scanned again.  A pair is also rejected as soon
+// run found by the last scan, or before any scan the pair's length as an
+// upper bound.  A step takes the largest key: an exact one is extracted, a
+// stale one is scanned (again).  A pair is also rejected as soon
 // as the runs still to come, none longer than the last one, cannot reach
 // m - E columns.
 //
@@ -104,11 +104,12 @@ __device__ __forceinline__ bool magnet_first_test(const uint64_t* rd, const uint
 }
 
 // The lane's pair held in registers: WM words of each sequence (zero past its
-// W words) and the mask of columns that left the search space.
+// W words), the vacant columns (m and above) of each word, and the mask of
+// columns that left the search space (vacant ones included).
 template <int WM>
 struct PairRegs {
     uint64_t rd[WM], rf[WM];
-    uint32_t gone[WM];
+    uint32_t vac[WM], gone[WM];
     uint32_t m, W;
 };
 
@@ -140,28 +141,27 @@ __device__ __forceinline__ bool meets_gone(const PairRegs<WM>& r, uint32_t a, ui
 
 // Free cells of word k of diagonal d (chosen per lane, |d| <= 31): the read
 // words around k funnel-shifted by d & 31 (those of k and k + 1 for d >= 0,
-// of k - 1 and k otherwise), compared with the reference word; vacant cells
-// and excluded columns are blocked.
+// of k - 1 and k otherwise), compared with the reference word; cells whose
+// read base lies outside the read, vacant columns and excluded columns are
+// blocked.
 template <int WM>
 __device__ __forceinline__ uint32_t free_word(const PairRegs<WM>& r, int k, bool pos, uint32_t sh) {
-    const int m = (int)r.m;
     const uint64_t p = k > 0 ? r.rd[k - 1] : 0ull;
     const uint64_t c = r.rd[k];
     const uint64_t n = k + 1 < WM ? r.rd[k + 1] : 0ull;
     const uint64_t H = pos ? n : c, L = pos ? c : p;
-    const uint32_t vc = vacant_word(k, m);
-    const uint32_t vh = pos ? vacant_word(k + 1, m) : vc, vl = pos ? vc : vacant_word(k - 1, m);
+    const uint32_t vp = k > 0 ? r.vac[k - 1] : ~0u, vc = r.vac[k], vn = k + 1 < WM ? r.vac[k + 1] : ~0u;
     const uint32_t lo = funnel((uint32_t)H, (uint32_t)L, sh);
     const uint32_t hi = funnel((uint32_t)(H >> 32), (uint32_t)(L >> 32), sh);
-    const uint32_t v = funnel(vh, vl, sh);
-    return ~((lo ^ (uint32_t)r.rf[k]) | (hi ^ (uint32_t)(r.rf[k] >> 32)) | v | vc | r.gone[k]);
+    const uint32_t v = funnel(pos ? vn : vc, pos ? vc : vp, sh);
+    return ~((lo ^ (uint32_t)r.rf[k]) | (hi ^ (uint32_t)(r.rf[k] >> 32)) | v | r.gone[k]);
 }
 
 // Ordering key of a run of diagonal i: longer first, then the smaller start,
 // then the smaller diagonal index (the order of extraction), so the best run
 // over all diagonals is the largest key.  Bit 0 is set when a scan found the
-// run; a key without it (the diagonal's free-cell count, start 0) is an
-// upper bound.  m <= 512 fits the 10-bit fields.
+// run; a key without it (length m, start 0) is an upper bound.  m <= 512
+// fits the 10-bit fields.
 __device__ __forceinline__ uint32_t run_key(uint32_t L, uint32_t s) { return (L << 17) | ((1023u - s) << 7); }
 __device__ __forceinline__ uint32_t diag_tag(uint32_t i, uint32_t scanned) { return ((63u - i) << 1) | scanned; }
 __device__ __forceinline__ uint32_t key_len(uint32_t key) { return key >> 17; }
@@ -198,17 +198,6 @@ __device__ uint32_t scan_key(const PairRegs<WM>& r, uint32_t i, int emax) {
     return best | diag_tag(i, 1u);
 }
 
-// The bound key of diagonal i before any scan: its number of free cells.
-template <int WM>
-__device__ uint32_t bound_key(const PairRegs<WM>& r, uint32_t i, int emax) {
-    const int d = (int)i - emax;
-    uint32_t pc = 0;
-#pragma unroll
-    for (int k = 0; k < WM; ++k)
-        if ((uint32_t)k < r.W) pc += popc(free_word<WM>(r, k, d >= 0, (uint32_t)d & 31u));
-    return pc ? run_key(pc, 0u) | diag_tag(i, 0u) : 0u;
-}
-
 // Threshold test of every pair; flag[p] = 0 for the pairs left undecided,
 // 1 for the others (the order the counting sort puts them in).
 template <int EMAX, bool GENERAL>
@@ -233,7 +222,7 @@ __global__ void __launch_bounds__(256) magnet_test_kernel(FilterParams P, uint8_
 
 // Refill a wave's idle lanes once this many are idle (or the wave's share
 // has fewer pairs left).
-constexpr uint32_t kRefillLanes = 16;
+constexpr uint32_t kRefillLanes = 8;
 
 template <int EMAX, int WM>
 __global__ void __launch_bounds__(256) magnet_kernel(FilterParams P, const uint32_t* order, const uint32_t* count) {
@@ -262,7 +251,7 @@ __global__ void __launch_bounds__(256) magnet_kernel(FilterParams P, const uint3
 #pragma unroll
     for (int k = 0; k < WM; ++k) {
         r.rd[k] = r.rf[k] = 0ull;
-        r.gone[k] = 0u;
+        r.vac[k] = r.gone[k] = ~0u;
     }
     uint64_t id = 0;
     uint32_t E = 0, covered = 0, it = 0;
@@ -285,13 +274,16 @@ __global__ void __launch_bounds__(256) magnet_kernel(FilterParams P, const uint3
                 for (int k = 0; k < WM; ++k) {
                     r.rd[k] = (uint32_t)k < r.W ? P.reads[off + k] : 0ull;
                     r.rf[k] = (uint32_t)k < r.W ? P.refs[off + k] : 0ull;
-                    r.gone[k] = 0u;
+                    r.vac[k] = r.gone[k] = vacant_word(k, (int)r.m);
                 }
                 covered = 0;
                 it = 0;
+                // Before any scan, m bounds every diagonal's best run (ties
+                // between bounds go to the first diagonal, so the first
+                // steps scan the diagonals in order).
                 for (int i = 0; i < D; ++i) {
                     const int d = i - EMAX;
-                    key[i * 64 + lane] = (d < 0 ? -d : d) <= (int)E ? bound_key<WM>(r, (uint32_t)i, EMAX) : 0u;
+                    key[i * 64 + lane] = (d < 0 ? -d : d) <= (int)E ? run_key(r.m, 0u) | diag_tag((uint32_t)i, 0u) : 0u;
                 }
                 busy = true;
             }
