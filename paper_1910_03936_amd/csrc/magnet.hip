@@ -113,14 +113,16 @@ struct PairRegs {
     uint32_t m, W;
 };
 
+// Bits of word k for the columns at or above t (a clamp and one shift of
+// a 64-bit constant, whose low half is zero once t passes the word).
+__device__ __forceinline__ uint32_t cols_from(int k, uint32_t t) {
+    const int x = min(max((int)t - 32 * k, 0), 32);
+    return (uint32_t)(0xFFFFFFFFull << x);
+}
+
 // Bits of columns [a, b) that fall in word k.
 __device__ __forceinline__ uint32_t cols_mask(int k, uint32_t a, uint32_t b) {
-    const uint32_t lo = 32u * (uint32_t)k;
-    const uint32_t x0 = a > lo ? min(a - lo, 32u) : 0u;
-    const uint32_t x1 = b > lo ? min(b - lo, 32u) : 0u;
-    const uint32_t hi_mask = x1 >= 32u ? ~0u : ((1u << x1) - 1u);
-    const uint32_t lo_mask = x0 >= 32u ? ~0u : ((1u << x0) - 1u);
-    return hi_mask & ~lo_mask;
+    return cols_from(k, a) & ~cols_from(k, b);
 }
 
 // Columns [a, b) leave the search space.
