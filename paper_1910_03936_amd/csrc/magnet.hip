@@ -57,9 +57,17 @@ __device__ __forceinline__ void word_longest(uint32_t x, uint32_t& L, uint32_t& 
 
 // Whether some diagonal has a run of at least `need` free cells: per word,
 // the run entering from below (carry + trailing free cells) and the runs
-// inside the word (x AND-ed with itself shifted by sh[0..5], which add up to
-// need - 1, leaves the starts of runs of need cells; none when need > 32).
-template <int EMAX, int I = 0>
+// inside the word.  How the runs inside a word are tested depends on `need`
+// (MODE):
+//   0: need > 32, no run inside one word is long enough (the carry finds the
+//      runs that cross words);
+//   1: 17 <= need <= 32, a run of 17 or more cells inside a 32-bit word
+//      covers bits 15 and 16, so the run through the word's middle (free
+//      cells up from bit 16 plus down from bit 15) is the only candidate;
+//   2: need <= 16, x AND-ed with itself shifted by sh[0..3], which add up to
+//      need - 1, leaves the starts of runs of need cells;
+//   3: any need (a wave whose lanes differ), the same with sh[0..5].
+template <int EMAX, int MODE, int I = 0>
 __device__ __forceinline__ void magnet_has_run(const WindowWords& q, uint32_t blocked, int E, uint32_t need,
                                                const uint32_t* sh, uint32_t* carry, uint32_t& found) {
     if constexpr (I < 2 * EMAX + 1) {
@@ -67,19 +75,31 @@ __device__ __forceinline__ void magnet_has_run(const WindowWords& q, uint32_t bl
         const bool on = (d < 0 ? -d : d) <= E;
         const uint32_t x = on ? ~(diag_raw<d>(q) | diag_vacant<d>(q) | blocked) : 0u;
         const uint32_t t = x == ~0u ? 32u : (uint32_t)__builtin_ctz(~x);
-        uint32_t r = x;
+        uint32_t in_word;
+        if constexpr (MODE == 0) {
+            in_word = 0u;
+        } else if constexpr (MODE == 1) {
+            // Both operands have 16 set bits on the far side, so the counts
+            // stop at 16.
+            const uint32_t up = (uint32_t)__builtin_ctz(~(x >> 16));
+            const uint32_t down = (uint32_t)__builtin_clz(~(x << 16));
+            in_word = (uint32_t)(up + down >= need);
+        } else {
+            uint32_t r = x;
 #pragma unroll
-        for (int j = 0; j < 6; ++j) r &= r >> sh[j];
+            for (int j = 0; j < (MODE == 2 ? 4 : 6); ++j) r &= r >> sh[j];
+            in_word = (uint32_t)(r != 0u);
+        }
         // (bitwise, so that no branch is taken per diagonal)
-        found |= (uint32_t)(carry[I] + t >= need) | (uint32_t)(r != 0u);
+        found |= (uint32_t)(carry[I] + t >= need) | in_word;
         carry[I] = x == ~0u ? carry[I] + 32u : (x == 0u ? 0u : (uint32_t)__builtin_clz(~x));
-        magnet_has_run<EMAX, I + 1>(q, blocked, E, need, sh, carry, found);
+        magnet_has_run<EMAX, MODE, I + 1>(q, blocked, E, need, sh, carry, found);
     }
 }
 
-template <int EMAX>
-__device__ __forceinline__ bool magnet_first_test(const uint64_t* rd, const uint64_t* rf, int W, int m, int E,
-                                                  uint32_t need) {
+template <int EMAX, int MODE>
+__device__ __forceinline__ bool magnet_first_test_mode(const uint64_t* rd, const uint64_t* rf, int W, int m, int E,
+                                                       uint32_t need) {
     constexpr int D = 2 * EMAX + 1;
     uint32_t carry[D];
 #pragma unroll
@@ -96,11 +116,24 @@ __device__ __forceinline__ bool magnet_first_test(const uint64_t* rd, const uint
     uint32_t found = need == 0u ? 1u : 0u;
     for (int k = 0; k < W; ++k) {
         const WindowWords q = window_words_direct(rd, rf, k, W, m);
-        magnet_has_run<EMAX>(q, q.vc, E, need, sh, carry, found);
+        magnet_has_run<EMAX, MODE>(q, q.vc, E, need, sh, carry, found);
     }
 #pragma unroll
     for (int i = 0; i < D; ++i) found |= (uint32_t)(carry[i] >= need);
     return found != 0u;
+}
+
+// The in-word test is chosen once per wave: the one of the lanes' common
+// mode, else the general one.
+template <int EMAX>
+__device__ __forceinline__ bool magnet_first_test(const uint64_t* rd, const uint64_t* rf, int W, int m, int E,
+                                                  uint32_t need) {
+    const uint32_t mode = need > 32u ? 0u : (need >= 17u ? 1u : 2u);
+    const uint64_t all = __ballot(true);
+    if (__ballot(mode == 0u) == all) return magnet_first_test_mode<EMAX, 0>(rd, rf, W, m, E, need);
+    if (__ballot(mode == 1u) == all) return magnet_first_test_mode<EMAX, 1>(rd, rf, W, m, E, need);
+    if (__ballot(mode == 2u) == all) return magnet_first_test_mode<EMAX, 2>(rd, rf, W, m, E, need);
+    return magnet_first_test_mode<EMAX, 3>(rd, rf, W, m, E, need);
 }
 
 // The lane's pair held in registers: WM words of each sequence (zero past its
