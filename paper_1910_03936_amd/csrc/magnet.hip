@@ -19,10 +19,10 @@
 // excluded columns in registers and takes the next pair of the share when
 // its own is done.  Per diagonal it keeps one ordering key in LDS: the best
 // run found by the last scan, or before any scan the pair's length as an
-// upper bound.  A step takes the largest key: an exact one is extracted, a
-// stale one is scanned (again).  A pair is also rejected as soon
-// as the runs still to come, none longer than the last one, cannot reach
-// m - E columns.
+// upper bound.  A step takes the largest key, extracts it when it is exact,
+// and scans its diagonal (again).  A pair is also rejected as soon as the
+// runs still to come, none longer than the last one, cannot reach m - E
+// columns.
 //
 // A diagonal's longest run is found word by word: the run that enters a
 // 32-column word from below ends at the word's first blocked column (a
@@ -276,10 +276,10 @@ __global__ void __launch_bounds__(256) magnet_kernel(FilterParams P, const uint3
     // Each lane runs its own pair and takes a new one when it is done, so a
     // wave waits for no pair.  A step selects the largest key of the lane's
     // diagonals.  A key from a scan whose run still avoids the excluded
-    // columns is exact and is extracted; otherwise (a bound, or a run that an
-    // exclusion has cut) the diagonal is scanned again.  Excluding columns
-    // only shortens runs, so a stale key is never below the exact one and the
-    // largest exact key is the true best.
+    // columns is exact and is extracted; either way the diagonal is then
+    // scanned (again).  Excluding columns only shortens runs, so a stale key
+    // is never below the exact one and the largest exact key is the true
+    // best.
     PairRegs<WM> r;
     r.m = 0;
     r.W = 0;
@@ -331,9 +331,7 @@ __global__ void __launch_bounds__(256) magnet_kernel(FilterParams P, const uint3
             bool done = L == 0u, rejected = false;
             if (!done) {
                 const uint32_t s = key_start(best), i = key_diag(best);
-                if ((best & 1u) == 0u || meets_gone<WM>(r, s, s + L)) {
-                    key[i * 64 + lane] = scan_key<WM>(r, i, EMAX);
-                } else {
+                if ((best & 1u) != 0u && !meets_gone<WM>(r, s, s + L)) {
                     // Extraction: the run and one column on each side leave
                     // the search space.
                     ++it;
@@ -343,6 +341,10 @@ __global__ void __launch_bounds__(256) magnet_kernel(FilterParams P, const uint3
                     rejected = covered + (E + 1u - it) * L + E < r.m;
                     done = rejected || it > E || covered >= r.m;
                 }
+                // The winner is scanned (again): a bound, a run an exclusion
+                // cut, or the run just extracted, whose key stays the largest
+                // and would be the next step's stale winner.
+                if (!done) key[i * 64 + lane] = scan_key<WM>(r, i, EMAX);
             }
             if (done) {
                 P.cnt[0][id] = (uint16_t)(rejected ? E + 1u : min(r.m - covered, E + 1u));
