@@ -1,7 +1,8 @@
 """MAGNET on the GPU against the oracle: every threshold of the 250 bp
 workload, the uneven mix with and without offsets, lengths around every word
 edge (runs that reach the last word's top), E >= m, exact matches, isolated
-substitutions, and a range violation."""
+substitutions, batches large enough that lanes take new pairs as they finish,
+and a range violation."""
 from __future__ import annotations
 
 import numpy as np
@@ -66,6 +67,32 @@ def test_magnet_edge_lengths(gpu_ctx):
         b = to_device(q, gpu_ctx, per_pair=True, offsets=True, max_len=512, max_E=me)
         assert_parity(results(gpu_ctx.filter_magnet(b), q.n), _want(q), f"edges max_E={me}")
     gpu_ctx.check()
+
+
+@pytest.mark.parametrize("lens", [(260,), (100, 150, 250)])
+def test_magnet_refill_large_batch(gpu_ctx, lens):
+    # A wave's share of the undecided list exceeds its 64 lanes only in large
+    # batches (the grid is capped at what fits the chip), so only these make
+    # lanes take new pairs as they finish.  Related pairs only, so that most
+    # pairs pass the first test; 260 bp pairs keep 16 words per sequence in
+    # registers, the mix 8; per-pair lengths and thresholds, word offsets.
+    n = 1_000_000
+    w = pairgen.Workload("related pairs, E = floor(0.05 m), k <= 20", n, lens, 20, 0.0,
+                         e_num=5, e_den=100, seed=pairgen.SEED_BASE + 41)
+    p = pairgen.generate(w, 0, n)
+    b = to_device(p, gpu_ctx, per_pair=True, offsets=True)
+    acc, cnt = results(gpu_ctx.filter_magnet(b), n)[SS]
+    gpu_ctx.check()
+    E = p.E.astype(np.int64)
+    assert np.all(cnt.astype(np.int64) <= E + 1)
+    assert np.array_equal(acc.astype(bool), cnt.astype(np.int64) <= E)
+    ids = pairgen.sample_ids(n, 20000)
+    wa, wc = oracle.magnet_batch(p.reads[ids], p.refs[ids], p.len[ids], p.E[ids])
+    bad = np.nonzero((acc[ids] != wa) | (cnt[ids] != wc))[0]
+    assert bad.size == 0, (f"{bad.size} of {ids.size} sampled pairs differ, first id {ids[bad[0]]}: "
+                           f"gpu {acc[ids[bad[0]]]},{cnt[ids[bad[0]]]} oracle {wa[bad[0]]},{wc[bad[0]]}")
+    # every accepted pair (E > 0 here) went through the extraction kernel
+    assert (cnt <= E).mean() > 0.3
 
 
 def test_magnet_range_violation(gpu_ctx):
