@@ -378,11 +378,12 @@ def filters_workload(args):
     r10 = by_E["10"]["all three"]
     gbs = r10["hbm_GBps"]
     emit(args, r10["pairs_per_s"], r10["ms"],
-         f"{n} pairs, 250 bp, 2-bit packed, 70% unrelated, k~U{{0..40}}; SneakySnake, GateKeeper and Shouji on "
-         f"one map, plain launch; value at E=10",
+         f"{n} pairs, 250 bp, 2-bit packed, 70% unrelated, k~U{{0..40}}; SneakySnake, GateKeeper and Shouji in "
+         f"one call (at E=10: SneakySnake on the compacting engine, GateKeeper and Shouji on one map); "
+         f"value at E=10",
          {"pairs": n, "read_len": 250, "E": [0, 5, 10, 25], "filters": "each alone and all three"},
          {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-          "traffic": None, "kernel": "filter_kernel<Whole, E=10, plain> (all three stages)",
+          "traffic": None, "kernel": "one call at E=10: chunk_kernel<10> (SneakySnake) + whole_kernel<10> (GateKeeper and Shouji)",
           "kernel_ms": r10["ms"], "alg_bytes_per_pair": round(2 * W * 8 + 3 * (2 + 1 / 8), 3)},
          None, {"by_E": by_E})
     ctx.close()

@@ -125,7 +125,10 @@ paf_status paf_pack_host(const uint8_t* codes, uint32_t code_stride, const uint1
  * chunk_tiles; 6 tiles per chunk, 2 waves per block, passes of 2 windows
  * unless a layout was forced with paf_set_layout, whose waves_per_block,
  * chunk_tiles and pass widths then apply here too; chunk_tiles = 0 selects
- * the per-tile engine). */
+ * the per-tile engine).  Several stages share one map and one launch up to
+ * max_E 7; from max_E 8 SneakySnake runs as above in a launch of its own,
+ * and from max_E 15 GateKeeper and Shouji get a launch each too (all on
+ * `stream`, in order; the outputs are the same either way). */
 paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, const paf_out* out,
                       void* stream);
 

@@ -400,6 +400,29 @@ paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, co
     if ((st = check_out(out, filters)) != PAF_OK) return st;
     const int emax = emax_bucket((int)p.max_E);
     if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
+    // Several stages: one map for all of them up to max_E 7.  From 8 on,
+    // SneakySnake runs on its own compacting engine (faster than its share
+    // of the whole-map kernel), and from 15 on GateKeeper and Shouji get a
+    // kernel each (the combined kernel's per-lane state no longer fits at a
+    // useful occupancy).  Every launch writes only its own stages' outputs.
+    const bool several = (filters & (filters - 1u)) != 0u;
+    if (several && (emax >= 15 || (emax >= 8 && (filters & PAF_SNEAKYSNAKE)))) {
+        // Each group below is a single stage, or GateKeeper and Shouji
+        // together under max_E 15, which the test above does not split again.
+        const uint32_t rest = filters & ~(uint32_t)PAF_SNEAKYSNAKE;
+        uint32_t groups[3];
+        int ng = 0;
+        if (filters & PAF_SNEAKYSNAKE) groups[ng++] = PAF_SNEAKYSNAKE;
+        if (emax >= 15) {
+            if (rest & PAF_GATEKEEPER) groups[ng++] = PAF_GATEKEEPER;
+            if (rest & PAF_SHOUJI) groups[ng++] = PAF_SHOUJI;
+        } else if (rest) {
+            groups[ng++] = rest;
+        }
+        for (int i = 0; i < ng; ++i)
+            if ((st = paf_filter(ctx, batch, groups[i], out, stream)) != PAF_OK) return st;
+        return PAF_OK;
+    }
     set_outputs(p, out);
     const bool general = batch->len || batch->E || batch->word_offset;
     Engine eng = engine_for(filters);
