@@ -97,9 +97,11 @@ __device__ __forceinline__ void magnet_has_run(const WindowWords& q, uint32_t bl
     }
 }
 
-template <int EMAX, int MODE>
-__device__ __forceinline__ bool magnet_first_test_mode(const uint64_t* rd, const uint64_t* rf, int W, int m, int E,
-                                                       uint32_t need) {
+// rd, rf: the pair's words in memory, or (STAGED) the wave's LDS rows of the
+// tile, read at column `lane`.
+template <int EMAX, int MODE, bool STAGED>
+__device__ __forceinline__ bool magnet_first_test_mode(const uint64_t* rd, const uint64_t* rf, int lane,
+                                                       uint32_t wmax, int W, int m, int E, uint32_t need) {
     constexpr int D = 2 * EMAX + 1;
     uint32_t carry[D];
 #pragma unroll
@@ -115,7 +117,7 @@ __device__ __forceinline__ bool magnet_first_test_mode(const uint64_t* rd, const
     }
     uint32_t found = need == 0u ? 1u : 0u;
     for (int k = 0; k < W; ++k) {
-        const WindowWords q = window_words_direct(rd, rf, k, W, m);
+        const WindowWords q = STAGED ? window_words(rd, rf, lane, k, wmax, m) : window_words_direct(rd, rf, k, W, m);
         magnet_has_run<EMAX, MODE>(q, q.vc, E, need, sh, carry, found);
     }
 #pragma unroll
@@ -125,15 +127,18 @@ __device__ __forceinline__ bool magnet_first_test_mode(const uint64_t* rd, const
 
 // The in-word test is chosen once per wave: the one of the lanes' common
 // mode, else the general one.
-template <int EMAX>
-__device__ __forceinline__ bool magnet_first_test(const uint64_t* rd, const uint64_t* rf, int W, int m, int E,
-                                                  uint32_t need) {
+template <int EMAX, bool STAGED>
+__device__ __forceinline__ bool magnet_first_test(const uint64_t* rd, const uint64_t* rf, int lane, uint32_t wmax,
+                                                  int W, int m, int E, uint32_t need) {
     const uint32_t mode = need > 32u ? 0u : (need >= 17u ? 1u : 2u);
     const uint64_t all = __ballot(true);
-    if (__ballot(mode == 0u) == all) return magnet_first_test_mode<EMAX, 0>(rd, rf, W, m, E, need);
-    if (__ballot(mode == 1u) == all) return magnet_first_test_mode<EMAX, 1>(rd, rf, W, m, E, need);
-    if (__ballot(mode == 2u) == all) return magnet_first_test_mode<EMAX, 2>(rd, rf, W, m, E, need);
-    return magnet_first_test_mode<EMAX, 3>(rd, rf, W, m, E, need);
+    if (__ballot(mode == 0u) == all)
+        return magnet_first_test_mode<EMAX, 0, STAGED>(rd, rf, lane, wmax, W, m, E, need);
+    if (__ballot(mode == 1u) == all)
+        return magnet_first_test_mode<EMAX, 1, STAGED>(rd, rf, lane, wmax, W, m, E, need);
+    if (__ballot(mode == 2u) == all)
+        return magnet_first_test_mode<EMAX, 2, STAGED>(rd, rf, lane, wmax, W, m, E, need);
+    return magnet_first_test_mode<EMAX, 3, STAGED>(rd, rf, lane, wmax, W, m, E, need);
 }
 
 // The lane's pair held in registers: WM words of each sequence (zero past its
@@ -234,14 +239,32 @@ __device__ uint32_t scan_key(const PairRegs<WM>& r, uint32_t i, int emax) {
 }
 
 // Threshold test of every pair; flag[p] = 0 for the pairs left undecided,
-// 1 for the others (the order the counting sort puts them in).
+// 1 for the others (the order the counting sort puts them in).  Up to
+// max_E 7 the test is light and the kernel would wait on memory, so each
+// wave first stages its tile's words in LDS with loads that cover whole
+// rows (the per-tile engine's staging); above, each lane reads its pair's
+// words itself.
+constexpr int kTestStagedMaxE = 7;
+
 template <int EMAX, bool GENERAL>
 __global__ void __launch_bounds__(256) magnet_test_kernel(FilterParams P, uint8_t* flag) {
+    constexpr bool STAGED = EMAX <= kTestStagedMaxE;
+    extern __shared__ uint64_t lds[];
     const int lane = threadIdx.x & 63;
-    const uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int wave = threadIdx.x >> 6;
+    const uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (tile >= P.n_tiles) return;
     uint64_t off = 0;
     PairSlot s = load_slot<GENERAL>(P, tile, lane, off);
+    const uint64_t* rd = P.reads + off;
+    const uint64_t* rf = P.refs + off;
+    if constexpr (STAGED) {
+        uint64_t* rdL = lds + (size_t)wave * 2 * P.wmax * kLdsRow;
+        uint64_t* rfL = rdL + (size_t)P.wmax * kLdsRow;
+        stage_tile<GENERAL>(P, tile, lane, s, off, rdL, rfL);
+        rd = rdL;
+        rf = rfL;
+    }
     if (!s.in_batch) return;
     if (!s.valid) {
         P.cnt[0][s.id] = 0;
@@ -249,7 +272,7 @@ __global__ void __launch_bounds__(256) magnet_test_kernel(FilterParams P, uint8_
         return;
     }
     const uint32_t need = s.m / (s.E + 1u);
-    const bool found = magnet_first_test<EMAX>(P.reads + off, P.refs + off, (int)s.W, (int)s.m, (int)s.E, need);
+    const bool found = magnet_first_test<EMAX, STAGED>(rd, rf, lane, P.wmax, (int)s.W, (int)s.m, (int)s.E, need);
     if (!found) P.cnt[0][s.id] = (uint16_t)(s.E + 1u);
     else if (s.E == 0) P.cnt[0][s.id] = 0;
     flag[s.id] = found && s.E > 0 ? 0 : 1;
@@ -393,9 +416,14 @@ hipError_t launch_magnet(const FilterParams& p, int emax, uint8_t* flag, uint32_
     FilterParams arg = p;
     const uint32_t waves = 4;
     {
+        const size_t lds_t = emax <= kTestStagedMaxE ? filter_lds_bytes(waves, p.wmax) : 0;
+        if (lds_t > 65536) {
+            hipError_t e = hipFuncSetAttribute(kt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_t);
+            if (e != hipSuccess) return e;
+        }
         const uint32_t blocks = (uint32_t)((p.n_tiles + waves - 1) / waves);
         void* args[] = {&arg, &flag};
-        hipError_t e = hipLaunchKernel(kt, dim3(blocks), dim3(64 * waves), args, 0, s);
+        hipError_t e = hipLaunchKernel(kt, dim3(blocks), dim3(64 * waves), args, lds_t, s);
         if (e != hipSuccess) return e;
     }
     // Undecided pairs first (flag 0), in pair order.

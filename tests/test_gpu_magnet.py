@@ -31,10 +31,14 @@ def test_magnet_fixed_250bp(gpu_ctx, E):
 
 def test_magnet_uneven_offsets(gpu_ctx):
     p = pairgen.generate(pairgen.UNEVEN_MIX, 67, 4000)
-    want = _want(p)
-    for offsets in (True, False):
-        b = to_device(p, gpu_ctx, per_pair=True, offsets=offsets)
-        assert_parity(results(gpu_ctx.filter_magnet(b), p.n), want, f"uneven offsets={offsets}")
+    # also with every threshold at most 7 (the first test then stages the
+    # tile's words in LDS)
+    low = pairgen.Pairs(p.reads, p.refs, p.len, np.minimum(p.E, 7).astype(p.E.dtype), p.related, p.k)
+    for q, tag in ((p, "E<=15"), (low, "E<=7")):
+        want = _want(q)
+        for offsets in (True, False):
+            b = to_device(q, gpu_ctx, per_pair=True, offsets=offsets)
+            assert_parity(results(gpu_ctx.filter_magnet(b), q.n), want, f"uneven {tag} offsets={offsets}")
     gpu_ctx.check()
 
 
@@ -60,7 +64,7 @@ def test_magnet_edge_lengths(gpu_ctx):
     Ev = np.zeros(n, np.uint8)
     for i, (a, r, m, E) in enumerate(rows):
         R[i, :m], F[i, :m], L[i], Ev[i] = a, r, m, E
-    for me in (15, 31):
+    for me in (7, 15, 31):
         sel = np.nonzero(Ev <= me)[0]
         q = pairgen.Pairs(R[sel], F[sel], L[sel], Ev[sel], np.zeros(sel.size, np.uint8),
                           np.zeros(sel.size, np.uint16))
