@@ -8,9 +8,10 @@
 // of fixed size, excluded columns set to ones).  count = min(m - covered,
 // E + 1), accept = count <= E.
 //
-// One lane per pair, two kernels.  The first reads each pair's words
-// straight from memory and only asks whether some diagonal has a run of at
-// least ceil((m - E) / (E + 1)) = floor(m / (E + 1)) free cells: without one
+// One lane per pair, two kernels.  The first reads each pair's words (staged
+// through LDS up to max_E 7, straight from memory above) and only asks
+// whether some diagonal has a run of at least
+// ceil((m - E) / (E + 1)) = floor(m / (E + 1)) free cells: without one
 // the pair is rejected (Sec. 7.2's first test: E + 1 runs that short cannot
 // cover m - E columns), and with E = 0 the answer decides the pair; the
 // others are flagged.  A stable counting sort of the flags (the bucketing
