@@ -183,6 +183,39 @@ __device__ void whole_tile(const FilterParams& P, uint64_t tile, int lane, uint6
         }
     }
 
+    if constexpr (FS == PAF_GATEKEEPER && EMAX <= 10) {
+        // GateKeeper alone: the previous, current and next window's masks
+        // take turns in three arrays, so no window copies them on (the loop
+        // is unrolled by hand; its wave vote keeps the compiler from it).
+        // Above max_E 10 the third array would cost occupancy.
+        uint32_t Gx[D];
+        auto gk_window = [&](uint32_t w, const uint32_t (&Gpv)[D], const uint32_t (&Gcu)[D], uint32_t (&Gnx)[D]) {
+            if (ps.valid && w < ps.W) {
+                const uint32_t colpast = vacant_word((int)w, (int)m);  // columns >= m
+                gk_ham += popc(Gcu[EMAX] & ~colpast);
+                const WindowWords qn = window_words(rdL, rfL, lane, (int)w + 1, P.wmax, (int)m);
+                build_gk<EMAX>(qn, Gnx);
+                uint32_t Fw = ~0u;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    if (mask_E) {
+                        const int d = i - EMAX;
+                        if ((uint32_t)(d < 0 ? -d : d) > E) Gnx[i] = ~0u;
+                    }
+                    Fw &= amend_word(Gcu[i], Gpv[i], Gnx[i]);
+                }
+                gk_cnt += popc(Fw & ~colpast);
+            }
+        };
+        for (uint32_t w = 0;;) {
+            if (!wave_any(ps.valid && w < ps.W)) break;
+            gk_window(w++, Gp, Gc, Gx);
+            if (!wave_any(ps.valid && w < ps.W)) break;
+            gk_window(w++, Gc, Gx, Gp);
+            if (!wave_any(ps.valid && w < ps.W)) break;
+            gk_window(w++, Gx, Gp, Gc);
+        }
+    } else
     for (uint32_t w = 0; wave_any(ps.valid && w < ps.W); ++w) {
         const bool have = ps.valid && w < ps.W;
         if (have) {

@@ -74,6 +74,28 @@ def test_uneven_per_pair(gpu_ctx, filters):
     gpu_ctx.check()
 
 
+@pytest.mark.parametrize("lens,E", [((96,), 4), ((180,), 9), ((270,), 10), ((100,), 3), ((250,), 10)])
+def test_gatekeeper_alone_window_counts(gpu_ctx, lens, E):
+    """GateKeeper alone (its window loop takes three windows per turn) on
+    pairs of 3, 6, 9, 4 and 8 words, so that the loop ends at each of its
+    three checks; uniform and per-pair layouts, with and without offsets."""
+    w = pairgen.Workload("GateKeeper window counts", 3000, lens, 20, 0.5, fixed_E=E,
+                         seed=pairgen.SEED_BASE + 51)
+    p = pairgen.generate(w, 0, 3000)
+    want = oracle_for(p, GK)
+    b = to_device(p, gpu_ctx, per_pair=False, offsets=False)
+    assert_parity(results(gpu_ctx.filter(b, GK), p.n), want, f"m={lens[0]} uniform")
+    for offsets in (True, False):
+        b = to_device(p, gpu_ctx, per_pair=True, offsets=offsets)
+        assert_parity(results(gpu_ctx.filter(b, GK), p.n), want, f"m={lens[0]} per-pair offsets={offsets}")
+    # the uneven mix with thresholds capped at E (mixed word counts per wave)
+    u = pairgen.generate(pairgen.UNEVEN_MIX, 9, 2100)
+    q = pairgen.Pairs(u.reads, u.refs, u.len, np.minimum(u.E, E).astype(u.E.dtype), u.related, u.k)
+    b = to_device(q, gpu_ctx, per_pair=True, offsets=True)
+    assert_parity(results(gpu_ctx.filter(b, GK), q.n), oracle_for(q, GK), f"uneven E<={E}")
+    gpu_ctx.check()
+
+
 def _edge_pairs():
     rng = np.random.default_rng(11)
     rows = []
