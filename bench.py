@@ -137,6 +137,39 @@ def calibrate_copy(gib=2.0, reps=5):
     print(json.dumps({"copy_bytes_each_way": n * 8, "reps": reps}), flush=True)
 
 
+CALIB_MIXES = ("v_add_u32", "v_bitop3_b32", "v_bcnt_u32_b32", "probe: v_add_u32 + v_bitop3_b32",
+               "v_alignbit_b32", "v_pk_add_u16", "map: v_alignbit_b32 + v_bitop3_b32")
+PROBE_MIX = 3
+
+
+def valu_ceiling(mixes=None, waves_per_simd=(8,), iters=20000, reps=3):
+    """Measured VALU issue rate (G wave64 instructions/s) of known instruction
+    mixes: libpaf_calib.so's kernel runs `iters` turns of 16 inline-asm VALU
+    instructions per thread, timed with HIP events.  Returns
+    {mix name: {waves per SIMD: rate}}."""
+    import ctypes
+
+    import torch
+
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1910_03936_amd", "libpaf_calib.so"))
+    lib.paf_calib_valu.restype = ctypes.c_float
+    lib.paf_calib_valu.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p]
+    per_turn = lib.paf_calib_per_turn()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = torch.zeros(1, dtype=torch.int32, device="cuda")
+    res = {}
+    for mix in (range(len(CALIB_MIXES)) if mixes is None else mixes):
+        row = {}
+        for wps in waves_per_simd:
+            blocks = cus * wps            # 256-thread blocks: 4 waves, one per SIMD
+            ms = lib.paf_calib_valu(mix, blocks, iters, reps, ctypes.c_void_p(out.data_ptr()))
+            if ms <= 0:
+                raise RuntimeError(f"VALU calibration failed (code {ms})")
+            row[wps] = blocks * 4 * iters * per_turn / (ms / 1e3) / 1e9
+        res[CALIB_MIXES[mix]] = row
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,9 +192,18 @@ def main():
                          "(filter + verify) vs verifying every pair, at E = 5, 10, 25")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain copy kernel of known size (counter calibration)")
+    ap.add_argument("--calibrate-valu", action="store_true",
+                    help="only measure the VALU issue rate of known instruction mixes and print it")
+    ap.add_argument("--reps", type=int, default=3, help="timed repetitions of each calibration kernel")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.calibrate_valu:
+        r = valu_ceiling(waves_per_simd=(1, 2, 4, 8), reps=args.reps)
+        for k, v in r.items():
+            log(f"{k:40s} " + "  ".join(f"{w} waves/SIMD: {g:7.1f} G/s" for w, g in v.items()))
+        print(json.dumps({"valu_wave_instr_per_s_G": r, "model_line_G": VALU_PEAK_GIPS}), flush=True)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

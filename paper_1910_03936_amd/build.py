@@ -9,6 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpaf.so")
 SOURCES = ["filter.hip", "whole.hip", "mlp.hip", "api.hip", "stream.hip", "verify.hip", "magnet.hip"]
+# Measurement aid (VALU issue-rate calibration), a library of its own.
+CALIB_LIB = os.path.join(HERE, "libpaf_calib.so")
+CALIB_SOURCE = "calib.hip"
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -28,12 +31,13 @@ def _hipcc() -> str:
 
 
 def build(verbose: bool = False, jobs: int = 5) -> str:
-    """Compile every source to an object in _build/, then link libpaf.so."""
+    """Compile every source to an object in _build/, then link libpaf.so (and
+    the calibration library libpaf_calib.so)."""
     out_dir = os.path.join(HERE, "_build")
     os.makedirs(out_dir, exist_ok=True)
     procs = []
     objs = []
-    for src in SOURCES:
+    for src in SOURCES + [CALIB_SOURCE]:
         obj = os.path.join(out_dir, src.replace(".hip", ".o"))
         objs.append(obj)
         cmd = [_hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
@@ -52,9 +56,11 @@ def build(verbose: bool = False, jobs: int = 5) -> str:
     if failed:
         msg = "\n".join(f"--- {s}\n{o}" for s, o in failed)
         raise RuntimeError(f"hipcc failed:\n{msg}")
-    tmp = LIB + ".tmp"
-    subprocess.check_call([_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
-    os.replace(tmp, LIB)
+    calib_obj = objs.pop()
+    for lib, parts in ((LIB, objs), (CALIB_LIB, [calib_obj])):
+        tmp = lib + ".tmp"
+        subprocess.check_call([_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *parts])
+        os.replace(tmp, lib)
     return LIB
 
 
