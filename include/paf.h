@@ -115,6 +115,23 @@ paf_status paf_pack_host(const uint8_t* codes, uint32_t code_stride, const uint1
                          uint16_t uniform_len, const uint64_t* word_offset, uint32_t stride_words,
                          uint64_t n, uint64_t* words, int threads);
 
+/* Host encoder from sequence text (the host-side read encoder of Ch. 4,
+ * Sec. 4.2, into the two-bit codes of Ch. 5, Method 3).  All pointers
+ * [host], owned by the caller.
+ * seqs: n rows of row_stride bytes; row p holds the m(p) bases of sequence p
+ * as ASCII letters A, C, G, T (lower case a, c, g, t is accepted as the same
+ * base; the bytes after m(p) are not read).  len / uniform_len, word_offset /
+ * stride_words and words as in paf_pack_host; `threads` host threads (0 =
+ * library default).
+ * Every row is checked before anything is written: a byte inside a sequence
+ * that is not one of those letters (N, IUPAC codes, digits, NUL ...) returns
+ * PAF_ERR_ARG, a length outside [1, PAF_MAX_LEN], above row_stride or beyond
+ * stride_words returns PAF_ERR_RANGE, and in both cases `words` is left
+ * untouched. */
+paf_status paf_pack_ascii(const char* seqs, uint32_t row_stride, const uint16_t* len, uint16_t uniform_len,
+                          const uint64_t* word_offset, uint32_t stride_words, uint64_t n, uint64_t* words,
+                          int threads);
+
 /* Plain batched filter.  For every pair: stage its words,
  * build the 2E+1 diagonal match bit-vectors (neighbourhood map, Eq. 6.1 /
  * unweighted maze, Eq. 8.2) and run the requested decision stages on them:

@@ -28,7 +28,7 @@ STATUS = {0: "PAF_OK", 1: "PAF_ERR_ARG", 2: "PAF_ERR_RANGE", 3: "PAF_ERR_DEVICE"
           4: "PAF_ERR_NOMEM", 5: "PAF_ERR_STATE"}
 
 # Every symbol declared in include/paf.h.
-EXPORTS = ("paf_create", "paf_destroy", "paf_last_error", "paf_check", "paf_pack", "paf_pack_host",
+EXPORTS = ("paf_create", "paf_destroy", "paf_last_error", "paf_check", "paf_pack", "paf_pack_host", "paf_pack_ascii",
            "paf_filter", "paf_filter_partitioned", "paf_filter_magnet", "paf_verify", "paf_filter_persistent", "paf_autotune", "paf_set_layout", "paf_features",
            "paf_mlp_set_params", "paf_mlp_get_params", "paf_mlp_forward", "paf_mlp_train_step",
            "paf_mlp_predict", "paf_mlp_train", "paf_bucket", "paf_filter_ordered", "paf_filter_bucketed",
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
         "paf_check": ([P, P]),
         "paf_pack": ([P, P, U32, P, ctypes.c_uint16, P, U32, U64, P, P]),
         "paf_pack_host": ([P, U32, P, ctypes.c_uint16, P, U32, U64, P, I]),
+        "paf_pack_ascii": ([P, U32, P, ctypes.c_uint16, P, U32, U64, P, I]),
         "paf_filter": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
         "paf_filter_persistent": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P]),
         "paf_filter_partitioned": ([P, ctypes.POINTER(_Batch), U32, U32, ctypes.POINTER(_Out), P]),
@@ -136,6 +137,27 @@ def _check(status: int):
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def pack_ascii(seqs, threads: int = 0):
+    """Encode equal-length DNA strings (A/C/G/T, either case) into the planar
+    two-bit words of paf.h on the host (paf_pack_ascii): returns a numpy uint64
+    array of len(seqs) * ceil(m / 32) words, the rows back to back.  Raises
+    PafError (PAF_ERR_ARG) on any other letter."""
+    import numpy as np
+
+    load_library()
+    if not seqs:
+        raise ValueError("no sequences")
+    m = len(seqs[0])
+    if any(len(x) != m for x in seqs):
+        raise ValueError("sequences differ in length")
+    rows = np.frombuffer("".join(seqs).encode("latin-1"), dtype=np.uint8)
+    W = words_for(m)
+    out = np.zeros(len(seqs) * W, np.uint64)
+    _check(_lib.paf_pack_ascii(rows.ctypes.data_as(ctypes.c_void_p), m, None, m, None, W, len(seqs),
+                               out.ctypes.data_as(ctypes.c_void_p), threads))
+    return out
 
 
 def _stream(stream=None):

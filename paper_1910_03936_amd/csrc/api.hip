@@ -350,32 +350,54 @@ paf_status paf_pack(paf_ctx* ctx, const uint8_t* codes, uint32_t code_stride, co
     return PAF_OK;
 }
 
-paf_status paf_pack_host(const uint8_t* codes, uint32_t code_stride, const uint16_t* len,
-                         uint16_t uniform_len, const uint64_t* word_offset, uint32_t stride_words,
-                         uint64_t n, uint64_t* words, int threads) {
-    if (!codes || !words) return fail(PAF_ERR_ARG, "codes/words is NULL");
-    if (n == 0) return fail(PAF_ERR_ARG, "n is zero");
-    if (!len && (uniform_len < 1 || uniform_len > PAF_MAX_LEN))
-        return fail(PAF_ERR_RANGE, "uniform_len outside [1, PAF_MAX_LEN]");
+}  // extern "C"
+
+namespace {
+// Host encoding of n rows into the planar two-bit words (layout of paf.h).
+// code(byte) gives the base value 0..3, or a value above 3 for a byte that is
+// not a base.  The rows are validated first (lengths against the stride, every
+// byte of every row); only when all are good are the words written, so a
+// rejected call leaves `words` untouched.  Returns 0, 1 (bad byte) or 2 (bad
+// length).
+template <typename Code>
+int pack_rows_host(const uint8_t* rows, uint32_t row_stride, const uint16_t* len, uint16_t uniform_len,
+                   const uint64_t* word_offset, uint32_t stride_words, uint64_t n, uint64_t* words,
+                   int threads, Code code) {
     if (threads <= 0) threads = (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
     std::vector<int> bad((size_t)threads, 0);
-    auto work = [&](int t) {
-        const uint64_t a = n * (uint64_t)t / threads, b = n * (uint64_t)(t + 1) / threads;
+    auto span = [&](int t, uint64_t& a, uint64_t& b) {
+        a = n * (uint64_t)t / threads;
+        b = n * (uint64_t)(t + 1) / threads;
+    };
+    auto check = [&](int t) {
+        uint64_t a, b;
+        span(t, a, b);
+        for (uint64_t p = a; p < b && !bad[t]; ++p) {
+            const uint32_t m = len ? len[p] : uniform_len;
+            if (m < 1 || m > PAF_MAX_LEN || m > row_stride || (!word_offset && words_for(m) > stride_words)) {
+                bad[t] = 2;
+                break;
+            }
+            const uint8_t* row = rows + p * (uint64_t)row_stride;
+            for (uint32_t j = 0; j < m; ++j)
+                if (code(row[j]) > 3u) {
+                    bad[t] = 1;
+                    break;
+                }
+        }
+    };
+    auto encode = [&](int t) {
+        uint64_t a, b;
+        span(t, a, b);
         for (uint64_t p = a; p < b; ++p) {
             const uint32_t m = len ? len[p] : uniform_len;
-            if (m < 1 || m > PAF_MAX_LEN || m > code_stride ||
-                (!word_offset && words_for(m) > stride_words)) {
-                bad[t] = 2;
-                continue;
-            }
-            const uint8_t* row = codes + p * (uint64_t)code_stride;
+            const uint8_t* row = rows + p * (uint64_t)row_stride;
             uint64_t* dst = words + (word_offset ? word_offset[p] : p * (uint64_t)stride_words);
             for (uint32_t k = 0; k < words_for(m); ++k) {
                 uint32_t lo = 0, hi = 0;
                 const uint32_t cnt = std::min(32u, m - 32u * k);
                 for (uint32_t j = 0; j < cnt; ++j) {
-                    const uint32_t v = row[32u * k + j];
-                    if (v > 3u) bad[t] = 1;
+                    const uint32_t v = code(row[32u * k + j]);
                     lo |= (v & 1u) << j;
                     hi |= ((v >> 1) & 1u) << j;
                 }
@@ -383,12 +405,62 @@ paf_status paf_pack_host(const uint8_t* codes, uint32_t code_stride, const uint1
             }
         }
     };
-    std::vector<std::thread> pool;
-    for (int t = 1; t < threads; ++t) pool.emplace_back(work, t);
-    work(0);
-    for (auto& th : pool) th.join();
-    for (int v : bad)
-        if (v) return fail(PAF_ERR_RANGE, v == 1 ? "base code above 3" : "pair length outside range or stride");
+    auto run = [&](auto&& f) {
+        std::vector<std::thread> pool;
+        for (int t = 1; t < threads; ++t) pool.emplace_back(f, t);
+        f(0);
+        for (auto& th : pool) th.join();
+    };
+    run(check);
+    int worst = 0;
+    for (int v : bad) worst = std::max(worst, v);
+    if (worst) return worst;
+    run(encode);
+    return 0;
+}
+
+// ASCII bases: A/a = 0, C/c = 1, G/g = 2, T/t = 3; every other byte 0xFF.
+struct AsciiTable {
+    uint8_t v[256];
+    AsciiTable() {
+        memset(v, 0xFF, sizeof(v));
+        const char* up = "ACGT";
+        const char* lo = "acgt";
+        for (int i = 0; i < 4; ++i) {
+            v[(uint8_t)up[i]] = (uint8_t)i;
+            v[(uint8_t)lo[i]] = (uint8_t)i;
+        }
+    }
+};
+const AsciiTable kAscii;
+}  // namespace
+
+extern "C" {
+
+paf_status paf_pack_host(const uint8_t* codes, uint32_t code_stride, const uint16_t* len,
+                         uint16_t uniform_len, const uint64_t* word_offset, uint32_t stride_words,
+                         uint64_t n, uint64_t* words, int threads) {
+    if (!codes || !words) return fail(PAF_ERR_ARG, "codes/words is NULL");
+    if (n == 0) return fail(PAF_ERR_ARG, "n is zero");
+    if (!len && (uniform_len < 1 || uniform_len > PAF_MAX_LEN))
+        return fail(PAF_ERR_RANGE, "uniform_len outside [1, PAF_MAX_LEN]");
+    const int r = pack_rows_host(codes, code_stride, len, uniform_len, word_offset, stride_words, n, words, threads,
+                                 [](uint8_t b) { return (uint32_t)b; });
+    if (r) return fail(PAF_ERR_RANGE, r == 1 ? "base code above 3" : "pair length outside range or stride");
+    return PAF_OK;
+}
+
+paf_status paf_pack_ascii(const char* seqs, uint32_t row_stride, const uint16_t* len, uint16_t uniform_len,
+                          const uint64_t* word_offset, uint32_t stride_words, uint64_t n, uint64_t* words,
+                          int threads) {
+    if (!seqs || !words) return fail(PAF_ERR_ARG, "seqs/words is NULL");
+    if (n == 0) return fail(PAF_ERR_ARG, "n is zero");
+    if (!len && (uniform_len < 1 || uniform_len > PAF_MAX_LEN))
+        return fail(PAF_ERR_RANGE, "uniform_len outside [1, PAF_MAX_LEN]");
+    const int r = pack_rows_host(reinterpret_cast<const uint8_t*>(seqs), row_stride, len, uniform_len, word_offset,
+                                 stride_words, n, words, threads, [](uint8_t b) { return (uint32_t)kAscii.v[b]; });
+    if (r == 1) return fail(PAF_ERR_ARG, "a byte that is not A, C, G or T (either case) inside a sequence");
+    if (r == 2) return fail(PAF_ERR_RANGE, "pair length outside range or stride");
     return PAF_OK;
 }
 
