@@ -575,3 +575,161 @@ def test_magnet_first_run_test_is_implied_by_the_final_one():
             acc, cnt, segs = oracle.magnet(p.reads[i], p.refs[i], E, with_segments=True)
             if segs[0][2] < need:
                 assert not acc and cnt == E + 1
+
+
+# ---------------------------------------------------------------- decision rules that
+# the closed forms above leave open.  Each pin below is also run against a
+# deliberately altered copy of the oracle (tests/mutants.py) to show that the
+# alteration it is meant to catch makes it fail.
+from mutants import mutant  # noqa: E402
+
+GK_OR = ("F[c] = (uint8_t)(F[c] & A[c]);", "F[c] = (uint8_t)(F[c] | A[c]);")
+GK_VACANT_ONE = ("G[c] = (uint8_t)map_cell(read, ref, m, c, d, 0);",
+                 "G[c] = (uint8_t)map_cell(read, ref, m, c, d, 1);")
+GK_SHIFTS_UNAMENDED = ("        amend(G, A, m);\n        for (int c = 0; c < m; ++c) F[c]",
+                       "        if (d == 0) amend(G, A, m); else memcpy(A, G, (size_t)m);\n"
+                       "        for (int c = 0; c < m; ++c) F[c]")
+SH_FIRST_TIED = ("(z > best_z || (z == best_z && lead && !best_lead))", "(z > best_z)")
+SH_STORE_ON_EQUAL = ("if (best_z > zs)", "if (best_z >= zs)")
+SH_REVERSED_ORDER = ("        for (int d = -E; d <= E; ++d) {\n            uint8_t v[4];",
+                     "        for (int d = E; d >= -E; --d) {\n            uint8_t v[4];")
+MG_LATER_START = ("if (L > best) { best = L; best_c = c; best_d = d; }",
+                  "if (L >= best) { best = L; best_c = c; best_d = d; }")
+
+
+def _gk_masks(read, ref, E):
+    """G_d straight from the definition (Sec. 5.2.2 with SHD's zero fill,
+    Sec. 3.2.3): bit c = 1 when ref[c] != read[c + d], vacant read index 0."""
+    m = len(ref)
+    out = {}
+    for d in range(-E, E + 1):
+        out[d] = np.array([0 if not 0 <= c + d < m else int(ref[c] != read[c + d]) for c in range(m)], np.uint8)
+    return out
+
+
+def test_gatekeeper_method2_worked_example():
+    g = read_golden("gatekeeper_method2.txt")
+    ref, read, E = enc(g["ref"]), enc(g["read"]), int(g["E"])
+    assert int((ref != read).sum()) == int(g["hamming"])
+    # the hand-derived masks of the fixture, from the definition
+    G = _gk_masks(read, ref, E)
+    F = np.ones(len(ref), np.uint8)
+    for d in G:
+        F &= oracle.amend(G[d])
+    assert "".join(map(str, F)) == g["F"]
+    assert oracle.gatekeeper(read, ref, E) == (bool(int(g["accept"])), int(g["count"]))
+    for edit, key in ((GK_OR, "count_or"), (GK_VACANT_ONE, "count_vacant_one"),
+                      (GK_SHIFTS_UNAMENDED, "count_unamended_shifts")):
+        with mutant(edit):
+            assert oracle.gatekeeper(read, ref, E)[1] == int(g[key])
+
+
+def _shifted_pairs(n, m, E, seed):
+    """Reads that are the reference shifted by k, 1 <= |k| <= E (the bases
+    shifted in are random), with Hamming distance > E."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        ref = rng.integers(0, 4, m).astype(np.uint8)
+        k = int(rng.integers(1, E + 1)) * (1 if rng.random() < 0.5 else -1)
+        read = rng.integers(0, 4, m).astype(np.uint8)
+        for j in range(m):
+            if 0 <= j - k < m:
+                read[j] = ref[j - k]
+        if int((ref != read).sum()) > E:
+            out.append((read, ref, k))
+    return out
+
+
+def _gk_shift_pin_holds(cases, E):
+    return all(oracle.gatekeeper(read, ref, E) == (True, 0) for read, ref, _ in cases)
+
+
+@pytest.mark.parametrize("E", [1, 3, 10])
+def test_gatekeeper_pure_shift_counts_zero(E):
+    # Diagonal d = k matches everywhere and its vacant bits are zeros, so its
+    # amended mask is all zeros and so is the AND: count 0, accept, although
+    # the Hamming fast path does not apply (Secs. 5.2.1-5.2.2).
+    cases = _shifted_pairs(60, 100, E, seed=E)
+    assert _gk_shift_pin_holds(cases, E)
+    for edit in (GK_OR, GK_VACANT_ONE):
+        with mutant(edit):
+            assert not _gk_shift_pin_holds(cases, E), edit
+
+
+def _gk_and_invariant_holds(pairs, E):
+    """count <= ones(amend(G_d)) for every d: F is the AND of the amended masks."""
+    for read, ref in pairs:
+        if int((read != ref).sum()) <= E:
+            continue
+        cnt = oracle.gatekeeper(read, ref, E)[1]
+        for d, G in _gk_masks(read, ref, E).items():
+            if cnt > int(oracle.amend(G).sum()):
+                return False
+    return True
+
+
+def _gk_zeros_from_long_streaks(pairs, E):
+    """Every zero of F sits in a zero streak of some G_d that the amendment
+    keeps: three or more zeros, or a streak touching an end."""
+    for read, ref in pairs:
+        if int((read != ref).sum()) <= E:
+            continue
+        G = _gk_masks(read, ref, E)
+        m = len(ref)
+        F = np.ones(m, np.uint8)
+        for d in G:
+            F &= oracle.amend(G[d])
+        if int(F.sum()) != oracle.gatekeeper(read, ref, E)[1]:
+            return False
+        for c in np.nonzero(F == 0)[0]:
+            ok = False
+            for g in G.values():
+                if g[c]:
+                    continue
+                a = c
+                while a > 0 and g[a - 1] == 0:
+                    a -= 1
+                b = c
+                while b < m - 1 and g[b + 1] == 0:
+                    b += 1
+                if b - a + 1 >= 3 or a == 0 or b == m - 1:
+                    ok = True
+                    break
+            if not ok:
+                return False
+    return True
+
+
+def test_gatekeeper_and_of_amended_shifted_masks():
+    p = pairgen.generate(pairgen.SMALL_100BP.with_E(4), 0, 300)
+    pairs = [(p.reads[i], p.refs[i]) for i in range(p.n)]
+    assert _gk_and_invariant_holds(pairs, 4)
+    assert _gk_zeros_from_long_streaks(pairs, 4)
+    with mutant(GK_OR):
+        assert not _gk_and_invariant_holds(pairs, 4)
+    with mutant(GK_SHIFTS_UNAMENDED):
+        assert not _gk_zeros_from_long_streaks(pairs, 4)
+
+
+def test_shouji_tie_break_and_store_rule_worked_example():
+    g = read_golden("shouji_tie_store.txt")
+    ref, read, E = enc(g["ref"]), enc(g["read"]), int(g["E"])
+    assert oracle.shouji(read, ref, E, with_vector=True) == (bool(int(g["accept"])), int(g["count"]), g["S"])
+    with mutant(SH_FIRST_TIED):
+        assert oracle.shouji(read, ref, E, with_vector=True)[1:] == (int(g["count_first_tied"]), g["S_first_tied"])
+    with mutant(SH_STORE_ON_EQUAL):
+        assert oracle.shouji(read, ref, E, with_vector=True)[1:] == (int(g["count_store_on_equal"]),
+                                                                      g["S_store_on_equal"])
+    with mutant(SH_REVERSED_ORDER):
+        assert oracle.shouji(read, ref, E, with_vector=True)[1:] == (int(g["count_reversed_order"]),
+                                                                      g["S_reversed_order"])
+
+
+def test_magnet_tie_rule_worked_example():
+    g = read_golden("magnet_tie.txt")
+    ref, read, E = enc(g["ref"]), enc(g["read"]), int(g["E"])
+    segs = [tuple(int(x) for x in s.split(":")) for s in g["segments"].split(",")]
+    assert oracle.magnet(read, ref, E, with_segments=True) == (bool(int(g["accept"])), int(g["count"]), segs)
+    with mutant(MG_LATER_START):
+        assert oracle.magnet(read, ref, E)[1] == int(g["count_later_start_first"])
