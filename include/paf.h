@@ -19,6 +19,15 @@
  *  - No C++ exception crosses this interface.
  *  - A context serves one device; calls on one context from several threads
  *    must be serialized by the caller.
+ *  - Calls that use the context's own device memory (the persistent launch's
+ *    work-queue counter, the bucketing workspace of the bucketed and MAGNET
+ *    calls, the cost model's weights and training workspace) may be made on
+ *    different streams: the library orders them, a call on another stream
+ *    than the previous such call waiting on the device for that call's work
+ *    (an event the context records).  paf_filter, paf_filter_partitioned,
+ *    paf_verify, paf_pack and paf_features use no such memory and are not
+ *    ordered.  A stream under graph capture should keep such calls on that
+ *    one stream.
  *
  * Sequence encoding (Ch. 5, Method 3: two bits per base; the thesis fixes
  * A = 00 and T = 11, this library uses C = 01 and G = 10).  A sequence of m
@@ -139,11 +148,12 @@ paf_status paf_pack_ascii(const char* seqs, uint32_t row_stride, const uint16_t*
  * fast path plus amended shifted masks (Ch. 5, Sec. 5.2) and Shouji's
  * sliding-window search (Ch. 6, Sec. 6.2).  filters: mask of PAF_* bits.
  * SneakySnake alone runs on the compacting engine (see paf_layout's
- * chunk_tiles; 6 tiles per chunk, 2 waves per block, passes of 2 windows
- * unless a layout was forced with paf_set_layout, whose waves_per_block,
- * chunk_tiles and pass widths then apply here too; chunk_tiles = 0 selects
- * the per-tile engine).  Several stages share one map and one launch up to
- * max_E 7; from max_E 8 SneakySnake runs as above in a launch of its own,
+ * chunk_tiles; 2 waves per block, a first pass of 2 windows, then chunks of 4
+ * tiles and later passes of 2 windows up to max_E 8, 6 tiles and 3 windows
+ * up to 15, 6 and 2 above; unless a layout was forced with paf_set_layout,
+ * whose waves_per_block, chunk_tiles and pass widths then apply here too;
+ * chunk_tiles = 0 selects the per-tile engine).  Several stages share one
+ * map and one launch up to max_E 7; from max_E 8 SneakySnake runs as above in a launch of its own,
  * and from max_E 15 GateKeeper and Shouji get a launch each too (all on
  * `stream`, in order; the outputs are the same either way). */
 paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, const paf_out* out,
@@ -320,21 +330,21 @@ paf_status paf_filter_bucketed(paf_ctx* ctx, const paf_batch* batch, uint32_t fi
 paf_status paf_cost_levels(paf_ctx* ctx, const paf_batch* batch, uint8_t* key, void* stream);
 
 /* Stage 2: SneakySnake alone on the compacting engine, the pairs of each
- * chunk entering the first pass grouped into four classes by bits 2-3 of
- * their key (key: uint8 per pair [device], original order; class = (key &
- * 15) >> 2, class 0 first; the two pairs sharing a 128-byte line of sequence
- * words take the lower class of the two).  Any key gives the outputs of
- * paf_filter; a key that groups pairs of like cost makes the groups of 64
- * more even.  Layout as paf_filter_bucketed_local. */
+ * chunk still undecided after the first pass entering the later passes
+ * grouped into four classes by bits 2-3 of their key (key: uint8 per pair
+ * [device], original order; class = (key & 15) >> 2, class 0 first; a
+ * stable sort, skipped when a chunk keeps more than 320 pairs).  Any key
+ * gives the outputs of paf_filter; a key that groups pairs of like cost
+ * makes the groups of 64 more even.  Layout as paf_filter_bucketed_local. */
 paf_status paf_filter_keyed(paf_ctx* ctx, const paf_batch* batch, const uint8_t* key, const paf_out* out,
                             void* stream);
 
 /* Chunk-local learned bucketing (SneakySnake alone).  The cost model's
  * prediction puts every pair on one of 16 levels (width 2 obstacles, highest
- * first).  The compacting filter then groups the pairs of each of its chunks
- * into four classes of four levels before the first window (paf_filter_keyed),
- * so each group of 64 takes pairs of like cost, while the pairs stay in place
- * in memory (no global permutation, no gathers).  Model and filter are captured in one HIP graph per (batch,
+ * first).  The compacting filter then groups the undecided pairs of each of
+ * its chunks into four classes of four levels after the first pass
+ * (paf_filter_keyed), so each group of 64 takes pairs of like cost, while the
+ * pairs stay in place in memory (no global permutation, no gathers).  Model and filter are captured in one HIP graph per (batch,
  * layout, outputs).  Outputs as paf_filter, in the original order.  The
  * launch layout is the forced or autotuned one if it has chunk_tiles > 0,
  * else paf_filter's. */

@@ -72,6 +72,19 @@ paf_status check_batch(const paf_ctx* ctx, const paf_batch* b, uint32_t filters,
     return PAF_OK;
 }
 
+paf_status scratch_begin(paf_ctx* ctx, hipStream_t s) {
+    if (ctx->scratch_used && ctx->scratch_stream != s)
+        PAF_HIP(hipStreamWaitEvent(s, ctx->scratch_ev, 0), "hipStreamWaitEvent");
+    return PAF_OK;
+}
+
+void scratch_end(paf_ctx* ctx, hipStream_t s) {
+    if (hipEventRecord(ctx->scratch_ev, s) == hipSuccess) {
+        ctx->scratch_stream = s;
+        ctx->scratch_used = true;
+    }
+}
+
 }  // namespace paf
 
 namespace {
@@ -108,8 +121,16 @@ paf_layout default_layout() {
     return l;
 }
 
-// Launch shape of paf_filter's SneakySnake-only launch.
-paf_layout plain_layout() { return paf_layout{1u, 2u, 0u, 1u, 6u, 2u, 2u}; }
+// Launch shape of paf_filter's SneakySnake-only launch (measured best on
+// 10M pairs of 250 bp): two-wave blocks and a two-window first pass; up to
+// max_E 8, chunks of 4 tiles (the kernel runs five waves per SIMD, so a
+// wave's LDS must stay under 8 KB) and two-window later passes; from 9 to
+// 15, chunks of 6 tiles and three-window later passes; above, 6 and two.
+paf_layout plain_layout(int emax) {
+    if (emax <= 8) return paf_layout{1u, 2u, 0u, 1u, 4u, 2u, 2u};
+    if (emax <= 15) return paf_layout{1u, 2u, 0u, 1u, 6u, 2u, 3u};
+    return paf_layout{1u, 2u, 0u, 1u, 6u, 2u, 2u};
+}
 
 bool layout_ok(const paf_layout& l) {
     return l.lanes_per_pair == 1 &&
@@ -245,15 +266,14 @@ paf_status ensure_bucket_ws(paf_ctx* ctx, uint64_t n) {
 
 // Launch layout: the forced one, else the autotuned one for this class, else
 // the default (work queue for the persistent entry point; for orders given
-// by a permutation, a full grid of two-wave blocks, compacting 6-tile chunks
-// and two-window passes for SneakySnake alone, where measured dispatch by
-// the hardware beat the queue).
+// by a permutation, paf_filter's full grid of compacting chunks for
+// SneakySnake alone, where measured dispatch by the hardware beat the queue).
 paf_layout layout_for(paf_ctx* ctx, const FilterParams& p, int emax, bool queue_default = true) {
     if (ctx->layout_forced) return ctx->forced;
     auto it = ctx->tuned.find(std::make_tuple((int)p.wmax, emax, p.filters));
     if (it != ctx->tuned.end()) return it->second;
     if (queue_default) return default_layout();
-    return paf_layout{1u, 2u, 0u, 1u, 6u, 2u, 2u};
+    return plain_layout(emax);
 }
 
 void set_outputs(FilterParams& p, const paf_out* out) {
@@ -288,8 +308,10 @@ paf_status paf_create(paf_ctx** out, int device) {
     }
     c->d_queue = c->d_err + 1;
     if (hipMemset(c->d_err, 0, 2 * sizeof(uint32_t)) != hipSuccess ||
+        hipEventCreateWithFlags(&c->scratch_ev, hipEventDisableTiming) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         hipFree(c->d_err);
+        if (c->scratch_ev) (void)hipEventDestroy(c->scratch_ev);
         delete c;
         return fail(PAF_ERR_DEVICE, "device initialisation failed");
     }
@@ -302,6 +324,7 @@ paf_status paf_destroy(paf_ctx* ctx) {
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
     for (auto& kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+    if (ctx->scratch_ev) (void)hipEventDestroy(ctx->scratch_ev);
     hipFree(ctx->d_err);
     mlp_free(ctx->mlp);
     hipFree(ctx->ws_pred);
@@ -504,7 +527,7 @@ paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, co
     uint64_t units = p.n_tiles;
     // SneakySnake alone: the compacting engine, as a full grid of chunks
     // (a forced layout may set its chunk size and block shape, or turn it off).
-    const paf_layout PL = ctx->layout_forced ? ctx->forced : plain_layout();
+    const paf_layout PL = ctx->layout_forced ? ctx->forced : plain_layout(emax);
     if (eng == Engine::Snake && PL.chunk_tiles > 0) {
         eng = Engine::Chunk;
         p.chunk = PL.chunk_tiles;
@@ -539,7 +562,7 @@ paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t
     const bool general = batch->len || batch->E || batch->word_offset;
     // The compacting engine, as a full grid of chunks (a forced layout that
     // compacts sets the chunk size, block shape and pass widths).
-    const paf_layout PL = ctx->layout_forced && ctx->forced.chunk_tiles > 0 ? ctx->forced : plain_layout();
+    const paf_layout PL = ctx->layout_forced && ctx->forced.chunk_tiles > 0 ? ctx->forced : plain_layout(emax);
     p.chunk = PL.chunk_tiles;
     p.span0 = std::max(1u, PL.first_pass_windows);
     p.span = std::max(1u, PL.pass_windows);
@@ -566,6 +589,8 @@ paf_status paf_filter_magnet(paf_ctx* ctx, const paf_batch* batch, const paf_out
     if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
     set_outputs(p, out);
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    ScratchScope scope(ctx, (hipStream_t)stream);
+    if (scope.st != PAF_OK) return scope.st;
     if ((st = ensure_bucket_ws(ctx, p.n_pairs)) != PAF_OK) return st;
     PAF_HIP(launch_magnet(p, emax, ctx->ws_bucket, ctx->ws_counts, ctx->ws_perm, ctx->ws_hist, ctx->num_cus,
                           (hipStream_t)stream),
@@ -597,6 +622,8 @@ paf_status paf_filter_persistent(paf_ctx* ctx, const paf_batch* batch, uint32_t 
     if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
     set_outputs(p, out);
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    ScratchScope scope(ctx, (hipStream_t)stream);
+    if (scope.st != PAF_OK) return scope.st;
     const paf_layout L = layout_for(ctx, p, emax);
     return run_persistent(ctx, p, engine_for(filters), emax, L, (hipStream_t)stream, true);
 }
@@ -623,6 +650,8 @@ paf_status paf_autotune(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, 
     if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
     set_outputs(p, out);
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    ScratchScope scope(ctx, (hipStream_t)stream);
+    if (scope.st != PAF_OK) return scope.st;
     hipStream_t s = (hipStream_t)stream;
     const Engine eng = engine_for(filters);
     std::vector<paf_layout> cands;
@@ -701,6 +730,8 @@ paf_status paf_mlp_predict(paf_ctx* ctx, const paf_batch* batch, float* pred, vo
     if (!pred) return fail(PAF_ERR_ARG, "pred is NULL");
     if (!ctx->mlp_ready) return fail(PAF_ERR_STATE, "no cost model: call paf_mlp_set_params first");
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    ScratchScope scope(ctx, (hipStream_t)stream);
+    if (scope.st != PAF_OK) return scope.st;
     PAF_HIP(launch_learned_buckets(ctx->mlp, p, ctx->num_cus, pred, nullptr, (hipStream_t)stream),
             "cost model launch");
     return PAF_OK;
@@ -712,8 +743,10 @@ paf_status paf_bucket(paf_ctx* ctx, const paf_batch* batch, const float* pred, u
     paf_status st = check_batch(ctx, batch, PAF_SNEAKYSNAKE, p);
     if (st != PAF_OK) return st;
     if (!pred || !perm || !hist) return fail(PAF_ERR_ARG, "pred/perm/hist is NULL");
-    if ((st = ensure_bucket_ws(ctx, p.n_pairs)) != PAF_OK) return st;
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    if ((st = ensure_bucket_ws(ctx, p.n_pairs)) != PAF_OK) return st;
+    ScratchScope scope(ctx, (hipStream_t)stream);
+    if (scope.st != PAF_OK) return scope.st;
     hipStream_t s = (hipStream_t)stream;
     PAF_HIP(launch_bucket_from_pred(p, pred, ctx->ws_bucket, s), "bucket keys");
     PAF_HIP(launch_bucket_sort(ctx->ws_bucket, p.n_pairs, ctx->ws_counts, perm, hist, s), "bucket sort");
@@ -730,6 +763,8 @@ paf_status paf_filter_ordered(paf_ctx* ctx, const paf_batch* batch, uint32_t fil
     const int emax = emax_bucket((int)p.max_E);
     if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    ScratchScope scope(ctx, (hipStream_t)stream);
+    if (scope.st != PAF_OK) return scope.st;
     FilterParams q = p;
     q.perm = order;
     for (int f = 0; f < 3; ++f) {
@@ -757,6 +792,8 @@ paf_status paf_filter_bucketed(paf_ctx* ctx, const paf_batch* batch, uint32_t fi
     const int emax = emax_bucket((int)p.max_E);
     if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    ScratchScope scope(ctx, (hipStream_t)stream);
+    if (scope.st != PAF_OK) return scope.st;
     if ((st = ensure_bucket_ws(ctx, p.n_pairs)) != PAF_OK) return st;
     FilterParams q = p;
     q.perm = ctx->ws_perm;
@@ -796,16 +833,18 @@ paf_status paf_cost_levels(paf_ctx* ctx, const paf_batch* batch, uint8_t* key, v
     if (!key) return fail(PAF_ERR_ARG, "key is NULL");
     if (!ctx->mlp_ready) return fail(PAF_ERR_STATE, "no cost model: call paf_mlp_set_params first");
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    ScratchScope scope(ctx, (hipStream_t)stream);
+    if (scope.st != PAF_OK) return scope.st;
     PAF_HIP(launch_learned_buckets(ctx->mlp, p, ctx->num_cus, nullptr, key, (hipStream_t)stream, true),
             "cost model launch");
     return PAF_OK;
 }
 
 // Layout of the keyed compacting launch: the forced or tuned one if it
-// compacts, else two-wave blocks with 6-tile chunks and two-window passes.
+// compacts, else paf_filter's.
 paf_layout keyed_layout(paf_ctx* ctx, const FilterParams& p, int emax) {
     paf_layout L = layout_for(ctx, p, emax, false);
-    if (L.chunk_tiles == 0) L = paf_layout{1u, 2u, 0u, 1u, 6u, 2u, 2u};
+    if (L.chunk_tiles == 0) L = plain_layout(emax);
     return L;
 }
 
@@ -820,6 +859,8 @@ paf_status paf_filter_keyed(paf_ctx* ctx, const paf_batch* batch, const uint8_t*
     const int emax = emax_bucket((int)p.max_E);
     if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    ScratchScope scope(ctx, (hipStream_t)stream);
+    if (scope.st != PAF_OK) return scope.st;
     set_outputs(p, out);
     p.order_key = key;
     return run_persistent(ctx, p, Engine::Snake, emax, keyed_layout(ctx, p, emax), (hipStream_t)stream, true);
@@ -835,6 +876,8 @@ paf_status paf_filter_bucketed_local(paf_ctx* ctx, const paf_batch* batch, const
     const int emax = emax_bucket((int)p.max_E);
     if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    ScratchScope scope(ctx, (hipStream_t)stream);
+    if (scope.st != PAF_OK) return scope.st;
     if ((st = ensure_bucket_ws(ctx, p.n_pairs)) != PAF_OK) return st;
     set_outputs(p, out);
     FilterParams q = p;

@@ -209,11 +209,73 @@ __device__ __forceinline__ void chunk_map(const WindowWords& q, DT dead, uint32_
 template <int EMAX, bool GENERAL>
 struct ChunkLds {
     using DT = typename DeadMask<EMAX>::T;
-    uint64_t* ent;
-    DT* dead;
-    uint64_t* off;   // GENERAL only
-    uint32_t* acc;   // 2 K accept words (plain order)
+    uint64_t* ent;    // the list: K*64 entries
+    uint64_t* off;    // GENERAL only: word offset of each pair of the chunk (by pair index)
+    uint64_t* stage;  // first-pass words of one group (kStageRead rows of read words, then
+                      // kStageRef rows of reference words, 64 words each); after the first
+                      // pass, the keyed sort's buffer
+    DT* dead;         // dead-diagonal mask of each pair (by pair index)
+    uint32_t* acc;    // 2K accept words (plain order)
+    uint16_t* cnt;    // K*64 counts (plain order)
 };
+
+// The first pass's windows 0 and 1 read words 0..2 of the read and words 0
+// and 1 of the reference (all inside the rows' first 32-byte sector); those
+// are staged, one LDS row of 64 words per word index.
+constexpr int kStageRead = 3, kStageRef = 2, kStageRow = 64;
+constexpr int kStageArea = (kStageRead + kStageRef) * kStageRow;   // uint64 words per wave
+
+// The staged rows of pair `lane` of the group: window k's words (k + 1 <
+// kStageRead).  Rows past a pair's length were staged as zeros.
+__device__ __forceinline__ WindowWords window_words_staged(const uint64_t* st, int lane, int k, int m) {
+    WindowWords q;
+    const uint64_t* rd = st;
+    const uint64_t* rf = st + kStageRead * kStageRow;
+    const uint64_t p = k > 0 ? rd[(k - 1) * kStageRow + lane] : 0ull;
+    const uint64_t c = rd[k * kStageRow + lane];
+    const uint64_t n = rd[(k + 1) * kStageRow + lane];
+    const uint64_t f = rf[k * kStageRow + lane];
+    q.plo = (uint32_t)p; q.phi = (uint32_t)(p >> 32);
+    q.clo = (uint32_t)c; q.chi = (uint32_t)(c >> 32);
+    q.nlo = (uint32_t)n; q.nhi = (uint32_t)(n >> 32);
+    q.flo = (uint32_t)f; q.fhi = (uint32_t)(f >> 32);
+    q.vp = vacant_word(k - 1, m);
+    q.vc = vacant_word(k, m);
+    q.vn = vacant_word(k + 1, m);
+    return q;
+}
+
+// Window k's words read from memory, the read words carried over from window
+// k - 1 of the same pass (first = true at a pass's first window, which loads
+// all of them).
+struct Carry {
+    uint64_t c, n;
+};
+
+__device__ __forceinline__ WindowWords window_words_carried(const uint64_t* rd, const uint64_t* rf, int k,
+                                                            int W, int m, bool first, Carry& cy) {
+    WindowWords q;
+    uint64_t p, c;
+    if (first) {
+        p = (k > 0 && k - 1 < W) ? rd[k - 1] : 0ull;
+        c = k < W ? rd[k] : 0ull;
+    } else {
+        p = cy.c;
+        c = cy.n;
+    }
+    const uint64_t n = k + 1 < W ? rd[k + 1] : 0ull;
+    const uint64_t f = k < W ? rf[k] : 0ull;
+    cy.c = c;
+    cy.n = n;
+    q.plo = (uint32_t)p; q.phi = (uint32_t)(p >> 32);
+    q.clo = (uint32_t)c; q.chi = (uint32_t)(c >> 32);
+    q.nlo = (uint32_t)n; q.nhi = (uint32_t)(n >> 32);
+    q.flo = (uint32_t)f; q.fhi = (uint32_t)(f >> 32);
+    q.vp = vacant_word(k - 1, m);
+    q.vc = vacant_word(k, m);
+    q.vn = vacant_word(k + 1, m);
+    return q;
+}
 
 // PART: the maze is cut into sub-mazes of P.part columns, each solved on its
 // own (Sec. 8.6; SneakySnake-t of Sec. 9.3.1).  A lane then also tracks pe,
@@ -223,10 +285,25 @@ struct ChunkLds {
 // y replications each cross one, so after the y-th the snake moves on to pe
 // (a sub-maze then counts min(y, its fewest obstacles), the hardware's
 // min(y, w - sum x)).
+//
+// Passes.  The first pass takes the chunk's pairs in order, 64 at a time:
+// the words its first two windows read (read words 0..2, reference words 0
+// and 1, inside each row's first 32-byte sector) are loaded for the whole
+// group together, four lanes per sector, into LDS, and the group walks
+// windows [0, span0) from there (later windows of a wider first pass, and
+// every window above EMAX 8, read their words from memory).  The pairs still undecided are appended to the list (in key
+// order when a key is given) and the later passes take the list 64 at a time
+// through `span` windows each, reading their words from memory and carrying
+// a pair's read words from one window to the next.  Counts and accept bits
+// of the chunk are collected in LDS and written once at the end.
 template <int EMAX, bool GENERAL, bool PART>
 __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, int lane,
                             const ChunkLds<EMAX, GENERAL>& L) {
     constexpr int D = 2 * EMAX + 1;
+    // From EMAX 9 on the kernel is bound by instruction issue: there the
+    // staging's own instructions cost more than the waits it saves (measured
+    // at EMAX 10), and every window reads its words straight from memory.
+    constexpr bool STAGED = EMAX <= 8;
     using DT = typename DeadMask<EMAX>::T;
     const uint64_t slot0 = (uint64_t)chunk * K * 64u;
     const uint32_t n_here = (uint32_t)min<uint64_t>((uint64_t)K * 64u, P.n_pairs - slot0);
@@ -235,96 +312,23 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
         for (uint32_t j = (uint32_t)lane; j < 2 * K; j += 64) L.acc[j] = 0u;
     const bool mask_E = GENERAL ? (P.E != nullptr || P.uniform_E < (uint32_t)EMAX)
                                 : (P.uniform_E < (uint32_t)EMAX);
-    uint32_t n_ent = n_here;
-    // With a key per pair (the cost model's level), the first pass's list
-    // holds the chunk's pairs grouped by the key's top two bits (four cost
-    // classes, a stable counting sort by wave ballots), so each group of 64
-    // takes pairs of like cost.  Finer classes bought less than the sort
-    // cost them.
     const bool keyed = P.order_key != nullptr && plain_out;
-    if (keyed) {
-        constexpr uint32_t NB = 4, NONE = NB;
-        // Class of pair i of the chunk (NONE = no entry: outside the batch or
-        // outside its bounds), with its length and threshold.
-        auto key_of = [&](uint32_t i, ChunkEntry& t) -> uint32_t {
-            t = ChunkEntry{};
-            t.idx = i;
-            t.m = P.uniform_len;
-            t.E = P.uniform_E;
-            if (i >= n_here) return NONE;
-            const uint64_t slot = slot0 + i;
-            if (GENERAL) {
-                if (P.len) t.m = P.len[slot];
-                if (P.E) t.E = P.E[slot];
-                if (t.m < 1 || t.m > P.max_len || t.E > P.max_E) return NONE;
-            }
-            return (P.order_key[slot] & 15u) >> 2;
-        };
-        // The two pairs of a 128-byte line of sequence words (adjacent
-        // pairs) take the costlier class of the two, so they stay side by
-        // side in the list and their lines are fetched once.
-        auto line_key = [&](uint32_t b) -> uint32_t {
-            const uint32_t o = (uint32_t)__shfl_xor((int)b, 1);
-            return b < NONE && o < b ? o : b;
-        };
-        uint32_t base[NB];
-#pragma unroll
-        for (uint32_t v = 0; v < NB; ++v) base[v] = 0;
-        for (uint32_t g = 0; g < n_here; g += 64) {
-            ChunkEntry t;
-            const uint32_t b = line_key(key_of(g + (uint32_t)lane, t));
-#pragma unroll
-            for (uint32_t v = 0; v < NB; ++v) base[v] += (uint32_t)__builtin_popcountll(__ballot(b == v));
-        }
-        uint32_t run = 0;
-#pragma unroll
-        for (uint32_t v = 0; v < NB; ++v) {
-            const uint32_t c = base[v];
-            base[v] = run;
-            run += c;
-        }
-        n_ent = run;
-        for (uint32_t g = 0; g < n_here; g += 64) {
-            const uint32_t i = g + (uint32_t)lane;
-            ChunkEntry t;
-            const uint32_t b = line_key(key_of(i, t));
-            if (i < n_here) {
-                const uint64_t slot = slot0 + i;
-                if (b == NONE) {
-                    atomicOr(P.err, 1u);
-                    P.cnt[0][slot] = 0;
-                } else if (GENERAL) {
-                    L.off[i] = P.word_offset ? P.word_offset[slot] : slot * (uint64_t)P.stride_words;
-                }
-            }
-            uint32_t pos = 0;
-#pragma unroll
-            for (uint32_t v = 0; v < NB; ++v) {
-                const uint64_t mv = __ballot(b == v);
-                const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mv >> 32),
-                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mv, 0u));
-                if (b == v) pos = base[v] + below;
-                base[v] += (uint32_t)__builtin_popcountll(mv);
-            }
-            if (b < NONE) L.ent[pos] = chunk_pack(t);
-        }
-    }
+    uint32_t n_ent = 0;
     // Each pass walks windows [w, w + span) with the same lanes; the pairs
     // still undecided after it are regrouped for the next pass.
-    for (uint32_t w = 0, span = P.span0; n_ent > 0; w += span, span = P.span) {
+    for (uint32_t w = 0, span = P.span0; w == 0 || n_ent > 0; w += span, span = P.span) {
         wave_lds_sync();
+        const bool first_pass = w == 0;
+        const uint32_t n_in = first_pass ? n_here : n_ent;
         uint32_t n_out = 0;
-        for (uint32_t g = 0; g < n_ent; g += 64) {
+        for (uint32_t g = 0; g < n_in; g += 64) {
             const uint32_t i = g + (uint32_t)lane;
-            bool act = i < n_ent;
+            bool act = i < n_in;
             ChunkEntry t = {};
             DT dead = 0;
             uint64_t off = 0;
-            if (w == 0 && !keyed) {
+            if (first_pass) {
                 t.idx = i;
-                t.c = 0;
-                t.e = 0;
-                t.cont = false;
                 t.m = P.uniform_len;
                 t.E = P.uniform_E;
                 if (act) {
@@ -337,16 +341,44 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                         L.off[i] = off;
                         if (t.m < 1 || t.m > P.max_len || t.E > P.max_E) {
                             atomicOr(P.err, 1u);
-                            P.cnt[0][id] = 0;
+                            if (plain_out) L.cnt[i] = 0;
+                            else P.cnt[0][id] = 0;
                             act = false;
                         }
                     } else {
                         off = slot * (uint64_t)P.stride_words;
                     }
                 }
+                // Stage the group's first words: lane l takes word l % 4 of
+                // pair l / 4 + 16 r, so four lanes cover one 32-byte sector
+                // (word 3, and the reference's words 2 and 3, are not kept).
+                if constexpr (STAGED) {
+                    wave_lds_sync();
+                    const uint32_t k = (uint32_t)lane & 3u;
+                    const uint32_t Wl = act ? (t.m + 31u) >> 5 : 0u;
+                    const uint32_t offlo = (uint32_t)off, offhi = (uint32_t)(off >> 32);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int j = (lane >> 2) + 16 * r;
+                        uint32_t Wj;
+                        uint64_t o;
+                        if (GENERAL) {
+                            // Each row's length and offset come from the lane that owns it.
+                            Wj = (uint32_t)__shfl((int)Wl, j);
+                            o = ((uint64_t)(uint32_t)__shfl((int)offhi, j) << 32) | (uint32_t)__shfl((int)offlo, j);
+                        } else {
+                            Wj = g + (uint32_t)j < n_in ? (P.uniform_len + 31u) >> 5 : 0u;
+                            o = (slot0 + g + (uint32_t)j) * (uint64_t)P.stride_words;
+                        }
+                        if (k < (uint32_t)kStageRead) L.stage[k * kStageRow + j] = k < Wj ? P.reads[o + k] : 0ull;
+                        if (k < (uint32_t)kStageRef)
+                            L.stage[(kStageRead + k) * kStageRow + j] = k < Wj ? P.refs[o + k] : 0ull;
+                    }
+                    wave_lds_sync();
+                }
             } else if (act) {
                 t = chunk_unpack(L.ent[i]);
-                dead = t.cont ? L.dead[i] : (DT)0;
+                dead = t.cont ? L.dead[t.idx] : (DT)0;
                 off = GENERAL ? L.off[t.idx] : (slot0 + t.idx) * (uint64_t)P.stride_words;
             }
             const uint32_t m = act ? t.m : 0u;
@@ -359,8 +391,17 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
             // pe follows from c alone.
             uint32_t pe = PART ? (c / P.part + 1u) * P.part : 0u;
             uint32_t ep = t.ep;
+            Carry cy = {0ull, 0ull};
             for (uint32_t wk = w; wk < w + span && wave_any(act); ++wk) {
-                const WindowWords q = window_words_direct(P.reads + off, P.refs + off, (int)wk, W, (int)m);
+                WindowWords q;
+                if constexpr (STAGED) {
+                    q = (first_pass && wk + 1u < (uint32_t)kStageRead)
+                        ? window_words_staged(L.stage, lane, (int)wk, (int)m)
+                        : window_words_carried(P.reads + off, P.refs + off, (int)wk, act ? W : 0, (int)m,
+                                               first_pass ? wk + 1u == (uint32_t)kStageRead : wk == w, cy);
+                } else {
+                    q = window_words_direct(P.reads + off, P.refs + off, (int)wk, act ? W : 0, (int)m);
+                }
                 // Vacant cells only occur in the first window and near the
                 // pair's end.  A snake that entered inside a pipe sees the
                 // diagonals whose pipes ended before this window blocked in
@@ -473,12 +514,11 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                 // exactly when e <= E) or counted E + 1 edits.
                 if (live && (c >= m || e > E)) {
                     act = false;
-                    const uint64_t slot = slot0 + t.idx;
                     if (plain_out) {
-                        P.cnt[0][slot] = (uint16_t)e;
+                        L.cnt[t.idx] = (uint16_t)e;
                         if (e <= E) atomicOr(&L.acc[t.idx >> 5], 1u << (t.idx & 31u));
                     } else {
-                        P.cnt[0][P.perm[slot]] = (uint16_t)e;
+                        P.cnt[0][P.perm[slot0 + t.idx]] = (uint16_t)e;
                     }
                 }
                 const bool ncont = act && clear != 0u;
@@ -501,7 +541,8 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                 cont = ncont;
                 dead = cont ? dm : (DT)0;
             }
-            // Survivors go on to the next pass.
+            // Survivors go on to the next pass (written behind the read
+            // position: n_out + pre <= i).
             const uint64_t bal = __ballot(act);
             const uint32_t pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
@@ -512,11 +553,53 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                 u.cont = cont;
                 u.ep = PART ? ep : 0u;
                 L.ent[n_out + pre] = chunk_pack(u);
-                L.dead[n_out + pre] = dead;
+                if (cont) L.dead[t.idx] = dead;
             }
             n_out += (uint32_t)__builtin_popcountll(bal);
         }
         n_ent = n_out;
+        if (first_pass && keyed && n_ent > 1 && n_ent <= (uint32_t)kStageArea) {
+            // The undecided pairs enter the later passes grouped into four
+            // classes by the key's bits 2-3 (a stable counting sort by wave
+            // ballots, through the staging area), so each group of 64 takes
+            // pairs of like predicted cost.  (More survivors than the area
+            // holds keep their order: the key only orders work.)
+            wave_lds_sync();
+            constexpr uint32_t NB = 4;
+            uint32_t base[NB];
+#pragma unroll
+            for (uint32_t v = 0; v < NB; ++v) base[v] = 0;
+            for (uint32_t g = 0; g < n_ent; g += 64) {
+                const uint32_t i = g + (uint32_t)lane;
+                const uint32_t cls = i < n_ent ? (P.order_key[slot0 + ((uint32_t)L.ent[i] & 1023u)] & 15u) >> 2 : NB;
+#pragma unroll
+                for (uint32_t v = 0; v < NB; ++v) base[v] += (uint32_t)__builtin_popcountll(__ballot(cls == v));
+            }
+            uint32_t run = 0;
+#pragma unroll
+            for (uint32_t v = 0; v < NB; ++v) {
+                const uint32_t cv = base[v];
+                base[v] = run;
+                run += cv;
+            }
+            for (uint32_t g = 0; g < n_ent; g += 64) {
+                const uint32_t i = g + (uint32_t)lane;
+                const uint64_t v64 = i < n_ent ? L.ent[i] : 0ull;
+                const uint32_t cls = i < n_ent ? (P.order_key[slot0 + ((uint32_t)v64 & 1023u)] & 15u) >> 2 : NB;
+                uint32_t pos = 0;
+#pragma unroll
+                for (uint32_t v = 0; v < NB; ++v) {
+                    const uint64_t mv = __ballot(cls == v);
+                    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mv >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mv, 0u));
+                    if (cls == v) pos = base[v] + below;
+                    base[v] += (uint32_t)__builtin_popcountll(mv);
+                }
+                if (cls < NB) L.stage[pos] = v64;
+            }
+            wave_lds_sync();
+            for (uint32_t i = (uint32_t)lane; i < n_ent; i += 64) L.ent[i] = L.stage[i];
+        }
     }
     if (plain_out) {
         wave_lds_sync();
@@ -524,22 +607,38 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
             const uint64_t s0 = slot0 + 32u * j;
             if (s0 < P.n_pairs) P.acc[0][s0 / 32] = L.acc[j];
         }
+        // Counts: two per 4-byte store when the output is 4-byte aligned
+        // (slot0 is a multiple of 64).
+        uint16_t* dst = P.cnt[0] + slot0;
+        if (((uintptr_t)dst & 3u) == 0) {
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(L.cnt);
+            uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
+            for (uint32_t j = (uint32_t)lane; 2 * j + 1 < n_here; j += 64) d32[j] = src[j];
+            if ((n_here & 1u) && lane == 0) dst[n_here - 1] = L.cnt[n_here - 1];
+        } else {
+            for (uint32_t j = (uint32_t)lane; j < n_here; j += 64) dst[j] = L.cnt[j];
+        }
     }
 }
 
-// Bytes of one wave's list in LDS.
+// Bytes of one wave's LDS: list, offsets (general layout), staging / sort
+// area, dead masks, accept words and counts.
 template <int EMAX, bool GENERAL>
 __host__ __device__ constexpr size_t chunk_wave_bytes_t(uint32_t K) {
     using DT = typename DeadMask<EMAX>::T;
-    return (size_t)K * 64 * (8 + sizeof(DT) + (GENERAL ? 8 : 0)) + (size_t)K * 8;
+    return (size_t)K * 64 * (8 + (GENERAL ? 8 : 0) + sizeof(DT) + 2) + (size_t)kStageArea * 8 + (size_t)K * 8;
 }
 
+// Up to EMAX 8 the kernel is held to the registers of five waves per SIMD:
+// measured faster than four waves with the registers it would take otherwise.
 template <int EMAX, bool GENERAL, bool PART>
-__global__ void __launch_bounds__(512) chunk_kernel(FilterParams P) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(EMAX <= 8 ? 5 : 1)))
+chunk_kernel(FilterParams P) {
     extern __shared__ uint64_t lds[];
     using DT = typename DeadMask<EMAX>::T;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // Wave-uniform, so the LDS pointers below live in scalar registers.
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t K = P.chunk;
     const uint32_t NE = K * 64u;
     char* b = reinterpret_cast<char*>(lds) + (size_t)wave * chunk_wave_bytes_t<EMAX, GENERAL>(K);
@@ -552,9 +651,13 @@ __global__ void __launch_bounds__(512) chunk_kernel(FilterParams P) {
     } else {
         L.off = nullptr;
     }
+    L.stage = reinterpret_cast<uint64_t*>(b);
+    b += (size_t)kStageArea * 8;
     L.dead = reinterpret_cast<DT*>(b);
     b += (size_t)NE * sizeof(DT);
     L.acc = reinterpret_cast<uint32_t*>(b);
+    b += (size_t)K * 8;
+    L.cnt = reinterpret_cast<uint16_t*>(b);
     const uint32_t n_chunks = (P.n_tiles + K - 1) / K;
     if (P.queue == nullptr) {
         const uint32_t ch = blockIdx.x * (blockDim.x >> 6) + wave;

@@ -1090,6 +1090,8 @@ paf_status paf_mlp_forward(paf_ctx* ctx, const float* features, uint64_t n, floa
     if (!features || !out) return fail(PAF_ERR_ARG, "features/out is NULL");
     if (n == 0) return fail(PAF_ERR_ARG, "n is zero");
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    ScratchScope scope(ctx, (hipStream_t)stream);
+    if (scope.st != PAF_OK) return scope.st;
     hipStream_t s = (hipStream_t)stream;
     MlpDev& m = ctx->mlp;
     const uint64_t chunk = 65536;
@@ -1121,6 +1123,8 @@ paf_status paf_mlp_train_step(paf_ctx* ctx, const float* features, const float* 
     if (n == 0 || n > 65536) return fail(PAF_ERR_RANGE, "minibatch size must be in [1, 65536]");
     if (lr < 0.0f) return fail(PAF_ERR_ARG, "lr is negative");
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    ScratchScope scope(ctx, (hipStream_t)stream);
+    if (scope.st != PAF_OK) return scope.st;
     hipStream_t s = (hipStream_t)stream;
     if ((st = train_step(ctx, features, targets, (uint32_t)n, lr, s, loss)) != PAF_OK) return st;
     if (grads)
@@ -1136,6 +1140,8 @@ paf_status paf_mlp_train(paf_ctx* ctx, const float* features, const uint16_t* la
     if (n == 0 || batch == 0 || batch > 65536 || epochs == 0) return fail(PAF_ERR_RANGE, "bad n/batch/epochs");
     if (!(lr > 0.0f)) return fail(PAF_ERR_ARG, "lr must be positive");
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    ScratchScope scope(ctx, (hipStream_t)stream);
+    if (scope.st != PAF_OK) return scope.st;
     hipStream_t s = (hipStream_t)stream;
     float* tg = nullptr;
     float* lbuf = nullptr;

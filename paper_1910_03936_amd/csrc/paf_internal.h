@@ -61,6 +61,23 @@ paf_status hip_fail(hipError_t e, const char* what);
 paf_status check_batch(const paf_ctx* ctx, const paf_batch* b, uint32_t filters, FilterParams& p);
 inline uint32_t words_for(uint32_t m) { return (m + 31u) / 32u; }
 
+// Calls that use the context's own device memory (the work-queue counter,
+// the bucketing workspace, the cost model's weights and training workspace)
+// are ordered across streams: a call on another stream than the previous such
+// call first waits (on the device) for that call's work.  scratch_begin
+// before enqueueing, scratch_end after (outside any graph capture).
+paf_status scratch_begin(paf_ctx* ctx, hipStream_t s);
+void scratch_end(paf_ctx* ctx, hipStream_t s);
+struct ScratchScope {
+    paf_ctx* ctx;
+    hipStream_t s;
+    paf_status st;
+    ScratchScope(paf_ctx* c, hipStream_t st_) : ctx(c), s(st_), st(scratch_begin(c, st_)) {}
+    ~ScratchScope() {
+        if (st == PAF_OK) scratch_end(ctx, s);
+    }
+};
+
 #define PAF_HIP(call, what)                                        \
     do {                                                           \
         hipError_t e_ = (call);                                    \
@@ -146,4 +163,8 @@ struct paf_ctx {
     uint32_t* ws_counts = nullptr;
     uint32_t* ws_hist = nullptr;
     uint64_t ws_cap = 0;
+    // Ordering of the calls that use the memory above across streams.
+    hipEvent_t scratch_ev = nullptr;
+    hipStream_t scratch_stream = nullptr;
+    bool scratch_used = false;
 };

@@ -211,3 +211,35 @@ def test_ordered_filter_equals_plain(gpu_ctx, filters):
         o = order.to(torch.int32).cuda()
         assert_parity(results(gpu_ctx.filter_ordered(b, o, filters), p.n), want, "ordered")
     gpu_ctx.check()
+
+
+def test_scratch_calls_on_two_streams(gpu_ctx):
+    """Persistent launches (work-queue counter), MAGNET (bucketing workspace)
+    and the global-bucket pipeline, issued back to back on two streams of one
+    context: the library orders them, so every result equals the oracle's."""
+    p = pairgen.generate(pairgen.UNEVEN_MIX, 41, 20_000)
+    b = to_device(p, gpu_ctx, per_pair=True, offsets=True)
+    want = oracle_for(p, SS)
+    want_mg = oracle.magnet_batch(p.reads, p.refs, p.len, p.E)
+    gpu_ctx.set_layout({"lanes_per_pair": 1, "waves_per_block": 4, "blocks_per_cu": 1, "tiles_per_grab": 1,
+                        "chunk_tiles": 0})
+    try:
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        outs = []
+        torch.cuda.synchronize()
+        for rep in range(3):
+            for s in (s1, s2):
+                with torch.cuda.stream(s):
+                    o = gpu_ctx.alloc_out(p.n, SS, b.device)
+                    gpu_ctx.filter_persistent(b, SS, out=o, stream=s)
+                    m = gpu_ctx.alloc_out(p.n, SS, b.device)
+                    gpu_ctx.filter_magnet(b, out=m, stream=s)
+                    outs.append((o, m))
+        torch.cuda.synchronize()
+        for o, m in outs:
+            assert_parity(results(o, p.n), want, "persistent, two streams")
+            got = results(m, p.n)[SS]
+            assert np.array_equal(got[0], want_mg[0]) and np.array_equal(got[1], want_mg[1])
+    finally:
+        gpu_ctx.set_layout(None)
+    gpu_ctx.check()
