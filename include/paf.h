@@ -197,6 +197,23 @@ paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t
  * with a larger batch). */
 paf_status paf_filter_magnet(paf_ctx* ctx, const paf_batch* batch, const paf_out* out, void* stream);
 
+/* paf_filter_magnet without any allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments and outputs as paf_filter_magnet.
+ * Its workspace is not the context's: it is a static device array of the
+ * library, laid out for up to PAF_MAGNET_NOALLOC_MAX_PAIRS pairs (about
+ * 20 MiB), of which each device the library runs on holds one copy until the
+ * process ends; its address is looked up once per context by paf_create.  The
+ * call makes no hipMalloc, hipFree or other allocating call.  Every call on
+ * one device shares that array: calls that overlap on the device (other
+ * streams, other contexts of the device) race and their results are
+ * undefined; calls on one stream, or ordered by the caller, do not.  Nothing
+ * in the array needs clearing between calls.  n_pairs above the maximum
+ * returns PAF_ERR_RANGE and launches nothing; PAF_ERR_DEVICE if the array's
+ * address could not be looked up at paf_create. */
+#define PAF_MAGNET_NOALLOC_MAX_PAIRS 4194304
+paf_status paf_filter_magnet_noalloc(paf_ctx* ctx, const paf_batch* batch, const paf_out* out, void* stream);
+
 /* Verification of filtered pairs: dist[p] = min(edit distance, E+1) of the
  * pair's reference segment and read, over alignments that stay inside the
  * band of the 2E+1 diagonals the filter examined (Ukkonen's banded edit

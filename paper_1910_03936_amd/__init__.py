@@ -22,6 +22,7 @@ ALL_FILTERS = SNEAKYSNAKE | GATEKEEPER | SHOUJI
 MAX_LEN, MAX_E = 512, 31
 MAX_PART = 65535  # widest sub-maze of paf_filter_partitioned
 MAX_REPL = 31     # most replications (obstacles per sub-maze) of paf_filter_partitioned
+MAGNET_NOALLOC_MAX_PAIRS = 4194304   # largest batch of paf_filter_magnet_noalloc
 MLP_NPARAMS = 24961
 
 STATUS = {0: "PAF_OK", 1: "PAF_ERR_ARG", 2: "PAF_ERR_RANGE", 3: "PAF_ERR_DEVICE",
@@ -29,7 +30,7 @@ STATUS = {0: "PAF_OK", 1: "PAF_ERR_ARG", 2: "PAF_ERR_RANGE", 3: "PAF_ERR_DEVICE"
 
 # Every symbol declared in include/paf.h.
 EXPORTS = ("paf_create", "paf_destroy", "paf_last_error", "paf_check", "paf_pack", "paf_pack_host", "paf_pack_ascii",
-           "paf_filter", "paf_filter_partitioned", "paf_filter_magnet", "paf_verify", "paf_filter_persistent", "paf_autotune", "paf_set_layout", "paf_features",
+           "paf_filter", "paf_filter_partitioned", "paf_filter_magnet", "paf_filter_magnet_noalloc", "paf_verify", "paf_filter_persistent", "paf_autotune", "paf_set_layout", "paf_features",
            "paf_mlp_set_params", "paf_mlp_get_params", "paf_mlp_forward", "paf_mlp_train_step",
            "paf_mlp_predict", "paf_mlp_train", "paf_bucket", "paf_filter_ordered", "paf_filter_bucketed",
            "paf_filter_bucketed_local", "paf_cost_levels", "paf_filter_keyed", "paf_stream_filter")
@@ -99,6 +100,7 @@ def load_library(path: str = LIB_PATH):
         "paf_filter_partitioned": ([P, ctypes.POINTER(_Batch), U32, U32, ctypes.POINTER(_Out), P]),
         "paf_verify": ([P, ctypes.POINTER(_Batch), P, P, P]),
         "paf_filter_magnet": ([P, ctypes.POINTER(_Batch), ctypes.POINTER(_Out), P]),
+        "paf_filter_magnet_noalloc": ([P, ctypes.POINTER(_Batch), ctypes.POINTER(_Out), P]),
         "paf_autotune": ([P, ctypes.POINTER(_Batch), U32, ctypes.POINTER(_Out), P,
                           ctypes.POINTER(Layout), ctypes.POINTER(ctypes.c_float),
                           ctypes.POINTER(ctypes.c_float)]),

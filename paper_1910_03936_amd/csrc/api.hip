@@ -315,6 +315,11 @@ paf_status paf_create(paf_ctx** out, int device) {
         delete c;
         return fail(PAF_ERR_DEVICE, "device initialisation failed");
     }
+    // The static workspace of paf_filter_magnet_noalloc: its address on this
+    // device (the device is current here).  A failed lookup only disables
+    // that entry point.
+    c->magnet_scratch_err = magnet_noalloc_address(&c->magnet_scratch);
+    if (c->magnet_scratch_err != hipSuccess) c->magnet_scratch = nullptr;
     *out = c;
     return PAF_OK;
 }
@@ -594,6 +599,25 @@ paf_status paf_filter_magnet(paf_ctx* ctx, const paf_batch* batch, const paf_out
     if ((st = ensure_bucket_ws(ctx, p.n_pairs)) != PAF_OK) return st;
     PAF_HIP(launch_magnet(p, emax, ctx->ws_bucket, ctx->ws_counts, ctx->ws_perm, ctx->ws_hist, ctx->num_cus,
                           (hipStream_t)stream),
+            "MAGNET launch");
+    return PAF_OK;
+}
+
+paf_status paf_filter_magnet_noalloc(paf_ctx* ctx, const paf_batch* batch, const paf_out* out, void* stream) {
+    const uint32_t filters = PAF_SNEAKYSNAKE;   // output slot 0
+    FilterParams p;
+    paf_status st = check_batch(ctx, batch, filters, p);
+    if (st != PAF_OK) return st;
+    if ((st = check_out(out, filters)) != PAF_OK) return st;
+    if (p.n_pairs > (uint64_t)PAF_MAGNET_NOALLOC_MAX_PAIRS)
+        return fail(PAF_ERR_RANGE, "batch larger than the static workspace (PAF_MAGNET_NOALLOC_MAX_PAIRS pairs)");
+    const int emax = emax_bucket((int)p.max_E);
+    if (emax < 0) return fail(PAF_ERR_RANGE, "max_E exceeds PAF_MAX_E");
+    if (!ctx->magnet_scratch)
+        return hip_fail(ctx->magnet_scratch_err, "device address of the static MAGNET workspace");
+    set_outputs(p, out);
+    PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    PAF_HIP(launch_magnet_noalloc(p, emax, ctx->magnet_scratch, ctx->num_cus, (hipStream_t)stream),
             "MAGNET launch");
     return PAF_OK;
 }

@@ -406,6 +406,43 @@ const void* magnet_kernel_for(int emax) {
 
 }  // namespace
 
+// Workspace of paf_filter_magnet_noalloc: a static device array, one copy on
+// every device the library runs on, held until the process ends.  Laid out
+// as the bucketing workspace of paf_filter_magnet for up to
+// PAF_MAGNET_NOALLOC_MAX_PAIRS pairs: the list order (4 bytes per pair), the
+// flags of the first test (1 byte per pair), the counting sort's per-block
+// counts and its 16 totals, each part starting on a 256-byte boundary.  Every
+// byte a call reads was written earlier in the same call, so nothing needs
+// clearing between calls.
+namespace {
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kNoallocOrder = 0;
+constexpr size_t kNoallocFlag = align256(kNoallocOrder + (size_t)PAF_MAGNET_NOALLOC_MAX_PAIRS * 4);
+constexpr size_t kNoallocCounts = align256(kNoallocFlag + (size_t)PAF_MAGNET_NOALLOC_MAX_PAIRS);
+constexpr size_t kNoallocHist =
+    align256(kNoallocCounts + 16 * (((size_t)PAF_MAGNET_NOALLOC_MAX_PAIRS + 4095) / 4096) * 4);
+constexpr size_t kNoallocBytes = align256(kNoallocHist + 16 * 4);
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kNoallocBytes];
+
+size_t magnet_noalloc_bytes() { return kNoallocBytes; }
+
+// The device address of `scratch` on the current device (the host-side name
+// of the array is only a stand-in: kernels and copies take this address).
+hipError_t magnet_noalloc_address(uint8_t** ptr) {
+    *ptr = nullptr;
+    return hipGetSymbolAddress(reinterpret_cast<void**>(ptr), HIP_SYMBOL(scratch));
+}
+
+hipError_t launch_magnet_noalloc(const FilterParams& p, int emax, uint8_t* base, int num_cus, hipStream_t s) {
+    if (p.n_pairs > (uint64_t)PAF_MAGNET_NOALLOC_MAX_PAIRS || bucket_count_words(p.n_pairs) * 4 > kNoallocHist - kNoallocCounts)
+        return hipErrorInvalidValue;
+    return launch_magnet(p, emax, base + kNoallocFlag, reinterpret_cast<uint32_t*>(base + kNoallocCounts),
+                         reinterpret_cast<uint32_t*>(base + kNoallocOrder), reinterpret_cast<uint32_t*>(base + kNoallocHist),
+                         num_cus, s);
+}
+
 hipError_t launch_magnet(const FilterParams& p, int emax, uint8_t* flag, uint32_t* counts, uint32_t* order,
                          uint32_t* hist, int num_cus, hipStream_t s) {
     const bool general = p.len || p.E || p.word_offset;

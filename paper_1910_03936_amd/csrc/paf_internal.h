@@ -108,6 +108,12 @@ hipError_t launch_verify(const FilterParams& p, int emax, const uint32_t* sel, u
 // flag/counts/order/hist: the bucketing workspace (flag: n_pairs bytes).
 hipError_t launch_magnet(const FilterParams& p, int emax, uint8_t* flag, uint32_t* counts, uint32_t* order,
                          uint32_t* hist, int num_cus, hipStream_t s);
+// The same on the static workspace of paf_filter_magnet_noalloc (`base` is
+// its device address, from magnet_noalloc_address on the current device);
+// more pairs than it holds: hipErrorInvalidValue, nothing launched.
+hipError_t launch_magnet_noalloc(const FilterParams& p, int emax, uint8_t* base, int num_cus, hipStream_t s);
+hipError_t magnet_noalloc_address(uint8_t** ptr);
+size_t magnet_noalloc_bytes();
 
 // mlp.hip
 struct MlpDev {
@@ -163,6 +169,10 @@ struct paf_ctx {
     uint32_t* ws_counts = nullptr;
     uint32_t* ws_hist = nullptr;
     uint64_t ws_cap = 0;
+    // Device address of paf_filter_magnet_noalloc's static workspace on this
+    // context's device (NULL if the lookup failed, with its error).
+    uint8_t* magnet_scratch = nullptr;
+    hipError_t magnet_scratch_err = hipSuccess;
     // Ordering of the calls that use the memory above across streams.
     hipEvent_t scratch_ev = nullptr;
     hipStream_t scratch_stream = nullptr;
