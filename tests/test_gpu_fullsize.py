@@ -1,20 +1,23 @@
 """The benchmark workloads at their full sizes, in the launch configurations the
-benchmark times, checked on sampled pairs against the oracle one by one and on
-whole-batch properties (accept exactly when the count is at most E, SneakySnake's
-count saturated at E+1, and the launch variants agreeing with each other on
-every pair).
+benchmark times, checked against the oracle element by element.
 
-- 10M pairs of 250 bp at E = 0, 5, 10, 25: SneakySnake, GateKeeper and Shouji
-  on one map, and SneakySnake alone on the compacting engine;
-- 50M pairs of mixed lengths in the persistent launch with the autotuned
-  layout, the fixed per-tile layout and the learned local pipeline;
-- 200M pairs streamed from pinned host memory in 8M-pair chunks, plain and
-  learned;
-- the rows beyond the path on the 10M x 250 bp pairs: SneakySnake on
-  partitioned mazes (t = 5, 10, 25, 50) and in the hardware form (t = 8,
-  y = 3), MAGNET, and verification of SneakySnake's survivors (identical to
-  verifying every pair).
-"""
+- SneakySnake on every pair: 10M pairs of 250 bp at E = 0, 5, 10, 25 (the
+  compacting engine alone, the shared map with all three stages, and at
+  E >= 8 the whole-map kernel of the persistent launch with all stages), 50M
+  pairs of mixed lengths in the persistent launch (fixed and autotuned
+  layouts, learned local pipeline), and 200M pairs streamed from pinned host
+  memory in 8M-pair chunks (plain and learned);
+- the other decision stages on the deterministic subsample of every 16th
+  pair (pair id % 16 == 0): GateKeeper and Shouji at every E, SneakySnake-t
+  (t = 5, 10, 25, 50) and the hardware form (t = 8, y = 3), MAGNET and
+  verification of SneakySnake's survivors;
+- whole-batch properties everywhere (accept exactly when count <= E,
+  SneakySnake's count at most E+1) and agreement of the launch variants on
+  every pair.
+
+The oracle regenerates the pairs chunk by chunk from their ids (the
+generator is a pure function of seed and pair id), so no batch sits in host
+memory whole."""
 import numpy as np
 import pytest
 import torch
@@ -26,7 +29,9 @@ from gpu_util import results
 
 pytestmark = pytest.mark.gpu
 
-SS, ALL = paf.SNEAKYSNAKE, paf.ALL_FILTERS
+SS, GK, SH, ALL = paf.SNEAKYSNAKE, paf.GATEKEEPER, paf.SHOUJI, paf.ALL_FILTERS
+CHUNK = 2_000_000
+SUB = 16          # the subsample: every 16th pair
 
 
 def check_properties(got: dict, E):
@@ -37,14 +42,24 @@ def check_properties(got: dict, E):
         assert np.array_equal(acc == 1, cnt <= E), f"filter {f}: accept bit disagrees with the count"
 
 
-def check_sample(got: dict, s: pairgen.Pairs, ids: np.ndarray, E, filters: int):
-    want = oracle.filter_batch(s.reads, s.refs, s.len, E, filters)
-    ix = ids.astype(np.int64)
-    for f in want:
-        ga, gc = got[f][0][ix], got[f][1][ix]
-        bad = np.nonzero((ga != want[f][0]) | (gc != want[f][1]))[0]
-        assert bad.size == 0, (f"filter {f}: {bad.size} sampled mismatches, first pair ids {ix[bad[:5]]}: "
-                               f"gpu {ga[bad[:5]]}/{gc[bad[:5]]} oracle {want[f][0][bad[:5]]}/{want[f][1][bad[:5]]}")
+def _mismatch(label, ids, ga, gc, wa, wc):
+    bad = np.nonzero((ga != wa) | (gc != wc))[0]
+    assert bad.size == 0, (f"{label}: {bad.size} mismatches, first pair ids {ids[bad[:5]]}: gpu "
+                           f"{ga[bad[:5]]}/{gc[bad[:5]]} oracle {wa[bad[:5]]}/{wc[bad[:5]]}")
+
+
+def every_pair_snake(w: pairgen.Workload, n: int, got: dict, label: str):
+    """SneakySnake of every pair [0, n) of workload w against the oracle.
+    got: {E or None (the workload's own per-pair thresholds): [(name, accept
+    uint8[n], count uint16[n]), ...]}; the pairs are generated once per chunk
+    for all of them."""
+    for a in range(0, n, CHUNK):
+        q = pairgen.generate(w, a, min(CHUNK, n - a))
+        ids = np.arange(a, a + q.n)
+        for E, outs in got.items():
+            wa, wc = oracle.filter_batch(q.reads, q.refs, q.len, q.E if E is None else E, SS)[SS]
+            for name, acc, cnt in outs:
+                _mismatch(f"{label} {name} E={E}", ids, acc[a:a + q.n], cnt[a:a + q.n], wa, wc)
 
 
 @pytest.fixture(scope="module")
@@ -52,23 +67,34 @@ def fixed250(gpu_ctx):
     from paper_1910_03936_amd.batches import device_batch
     w = pairgen.FIXED_250BP
     b = device_batch(gpu_ctx, w, w.n_pairs, per_pair=False)
-    ids = pairgen.sample_ids(w.n_pairs, 5000)
-    return b, ids, pairgen.generate_ids(w, ids)
+    sub = np.arange(0, w.n_pairs, SUB, dtype=np.uint64)
+    return b, sub, pairgen.generate_ids(w, sub)
 
 
 @pytest.mark.parametrize("E", [0, 5, 10, 25])
-def test_full_size_fixed_250bp_all_filters(gpu_ctx, fixed250, E):
-    b, ids, s = fixed250
+def test_full_size_fixed_250bp(gpu_ctx, fixed250, E):
+    b, sub, s = fixed250
     b.uniform_E = E
     b.max_E = E
     n = b.n_pairs
-    got = results(gpu_ctx.filter(b, ALL), n)
-    check_properties(got, E)
-    check_sample(got, s, ids, np.full(s.n, E), ALL)
-    # SneakySnake alone runs the compacting engine: same decisions as on the shared map
-    alone = results(gpu_ctx.filter(b, SS), n)
-    assert np.array_equal(alone[SS][0], got[SS][0]) and np.array_equal(alone[SS][1], got[SS][1])
+    shared = results(gpu_ctx.filter(b, ALL), n)
+    check_properties(shared, E)
+    alone = results(gpu_ctx.filter(b, SS), n)[SS]
+    outs = [("compacting engine", alone[0], alone[1]), ("all stages in one call", shared[SS][0], shared[SS][1])]
+    if E >= 8:
+        # the whole-map kernel's SneakySnake (persistent launch, all stages)
+        whole = results(gpu_ctx.filter_persistent(b, ALL), n)
+        for f in (SS, GK, SH):
+            assert np.array_equal(whole[f][0], shared[f][0]) and np.array_equal(whole[f][1], shared[f][1]), \
+                f"E={E}: persistent whole-map launch and paf_filter disagree on filter {f}"
+        outs.append(("whole-map kernel", whole[SS][0], whole[SS][1]))
     gpu_ctx.check()
+    every_pair_snake(pairgen.FIXED_250BP.with_E(E), n, {E: outs}, "10M x 250 bp")
+    # GateKeeper and Shouji on every 16th pair
+    want = oracle.filter_batch(s.reads, s.refs, s.len, np.full(s.n, E), GK | SH)
+    ix = sub.astype(np.int64)
+    for f in (GK, SH):
+        _mismatch(f"filter {f} E={E}", ix, shared[f][0][ix], shared[f][1][ix], want[f][0], want[f][1])
 
 
 def test_full_size_uneven_50M(gpu_ctx):
@@ -79,24 +105,22 @@ def test_full_size_uneven_50M(gpu_ctx):
     _, Es = pairgen.lengths(w, 0, n)
     gpu_ctx.set_layout({"lanes_per_pair": 1, "waves_per_block": 4, "blocks_per_cu": 4, "tiles_per_grab": 2,
                         "chunk_tiles": 0})
-    fixed = results(gpu_ctx.filter_persistent(b, SS), n)
+    fixed = results(gpu_ctx.filter_persistent(b, SS), n)[SS]
     gpu_ctx.set_layout(None)
     tuned_layout, _, _ = gpu_ctx.autotune(b, SS)
     tuned = results(gpu_ctx.filter_persistent(b, SS), n)
     check_properties(tuned, Es)
-    ids = pairgen.sample_ids(n, 20000)
-    s = pairgen.generate_ids(w, ids)
-    check_sample(tuned, s, ids, s.E, SS)
-    for a, bb in zip(fixed[SS], tuned[SS]):
-        assert np.array_equal(a, bb), f"fixed layout and autotuned {tuned_layout} disagree"
-    # The learned local pipeline (model levels, then chunks ordered by level)
-    # with the initial weights: the decisions never depend on the model.
+    # The learned local pipeline (model levels, then the undecided pairs of
+    # each chunk ordered by level) with the initial weights: the decisions
+    # never depend on the model.
     gpu_ctx.mlp_set_params(pairgen.init_mlp_params())
-    learned = results(gpu_ctx.filter_bucketed_local(b), n)
-    for a, bb in zip(learned[SS], tuned[SS]):
-        assert np.array_equal(a, bb), "learned pipeline disagrees with the plain launch"
+    learned = results(gpu_ctx.filter_bucketed_local(b), n)[SS]
     gpu_ctx.check()
     gpu_ctx.set_layout(None)
+    del b
+    torch.cuda.empty_cache()
+    every_pair_snake(w, n, {None: [("fixed layout", *fixed), (f"autotuned {tuned_layout}", *tuned[SS]),
+                                   ("learned local", *learned)]}, "50M uneven")
 
 
 def test_full_size_stream_200M(gpu_ctx):
@@ -110,31 +134,20 @@ def test_full_size_stream_200M(gpu_ctx):
         o, st = paf.stream_filter(gpu_ctx, hb, 8_000_000, SS, learned)
         gpu_ctx.check()
         assert st["chunks"] == 25
-        out[learned] = results(o, n)
+        out[learned] = results(o, n)[SS]
     del hb
-    assert np.array_equal(out[False][SS][0], out[True][SS][0])
-    assert np.array_equal(out[False][SS][1], out[True][SS][1])
     _, Es = pairgen.lengths(w, 0, n)
-    check_properties(out[True], Es)
-    ids = pairgen.sample_ids(n, 20000)
-    s = pairgen.generate_ids(w, ids)
-    check_sample(out[True], s, ids, s.E, SS)
-
-
-def _sampled(got_acc, got_cnt, ids, want_acc, want_cnt, label):
-    ix = ids.astype(np.int64)
-    bad = np.nonzero((got_acc[ix] != want_acc) | (got_cnt[ix] != want_cnt))[0]
-    assert bad.size == 0, (f"{label}: {bad.size} sampled mismatches, first pair ids {ix[bad[:5]]}: "
-                           f"gpu {got_acc[ix][bad[:5]]}/{got_cnt[ix][bad[:5]]} oracle {want_acc[bad[:5]]}/"
-                           f"{want_cnt[bad[:5]]}")
+    check_properties({SS: out[True]}, Es)
+    every_pair_snake(w, n, {None: [("plain", *out[False]), ("learned", *out[True])]}, "200M streamed")
 
 
 @pytest.mark.parametrize("E", [5, 10, 25])
 def test_full_size_partitioned_and_hardware_form(gpu_ctx, fixed250, E):
-    b, ids, s = fixed250
+    b, sub, s = fixed250
     b.uniform_E = E
     b.max_E = E
     n = b.n_pairs
+    ix = sub.astype(np.int64)
     whole = results(gpu_ctx.filter(b, SS), n)[SS][1].astype(np.int64)
     prev = None
     for t, y in ((5, 0), (10, 0), (25, 0), (50, 0), (8, 3)):
@@ -146,7 +159,7 @@ def test_full_size_partitioned_and_hardware_form(gpu_ctx, fixed250, E):
             assert np.all(cnt.astype(np.int64) <= whole)
         else:
             wa, wc = oracle.sneakysnake_fpga_batch(s.reads, s.refs, s.len, E, t, y)
-        _sampled(acc, cnt, ids, wa, wc, f"E={E} t={t} y={y}")
+        _mismatch(f"E={E} t={t} y={y}", ix, acc[ix], cnt[ix], wa, wc)
         if t == 10:
             # t = 5 refines t = 10: never more obstacles
             assert np.all(prev <= cnt)
@@ -154,22 +167,23 @@ def test_full_size_partitioned_and_hardware_form(gpu_ctx, fixed250, E):
     gpu_ctx.check()
 
 
-@pytest.mark.parametrize("E", [5, 10])
+@pytest.mark.parametrize("E", [0, 5, 10, 25])
 def test_full_size_magnet(gpu_ctx, fixed250, E):
-    b, ids, s = fixed250
+    b, sub, s = fixed250
     b.uniform_E = E
     b.max_E = E
     n = b.n_pairs
     acc, cnt = results(gpu_ctx.filter_magnet(b), n)[SS]
     check_properties({SS: (acc, cnt)}, E)
     wa, wc = oracle.magnet_batch(s.reads, s.refs, s.len, E)
-    _sampled(acc, cnt, ids, wa, wc, f"MAGNET E={E}")
+    ix = sub.astype(np.int64)
+    _mismatch(f"MAGNET E={E}", ix, acc[ix], cnt[ix], wa, wc)
     gpu_ctx.check()
 
 
 @pytest.mark.parametrize("E", [5, 10, 25])
 def test_full_size_verify_survivors(gpu_ctx, fixed250, E):
-    b, ids, s = fixed250
+    b, sub, s = fixed250
     b.uniform_E = E
     b.max_E = E
     n = b.n_pairs
@@ -181,8 +195,9 @@ def test_full_size_verify_survivors(gpu_ctx, fixed250, E):
     d = paf.counts_u16(d_all).cpu().numpy().astype(np.uint16)
     assert np.all(d <= E + 1)
     want = oracle.banded_batch(s.reads, s.refs, s.len, np.full(s.n, E))
-    bad = np.nonzero(d[ids.astype(np.int64)] != want)[0]
-    assert bad.size == 0, f"E={E}: {bad.size} sampled distances differ from the oracle"
+    ix = sub.astype(np.int64)
+    bad = np.nonzero(d[ix] != want)[0]
+    assert bad.size == 0, f"E={E}: {bad.size} subsampled distances differ from the oracle, ids {ix[bad[:5]]}"
     # A pair within E edits always survives SneakySnake.
     acc = paf.accept_bits_to_bool(out[SS][0], n).cpu().numpy()
     assert np.all(acc[d <= E])
