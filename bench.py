@@ -205,7 +205,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="time the plain filter only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="fixed250",
-                    choices=["fixed250", "filters", "partitioned", "verify", "uneven", "learned-uneven", "stream"],
+                    choices=["fixed250", "filters", "partitioned", "verify", "accuracy", "uneven", "learned-uneven",
+                             "stream"],
                     help="fixed250 (default): 10M x 250 bp at E (plain and learned-bucketed); filters: the "
                          "same pairs at E = 0, 5, 10, 25 with SneakySnake, GateKeeper, Shouji and all three "
                          "on one map; uneven: 50M pairs of mixed lengths in the persistent launch, default "
@@ -213,7 +214,9 @@ def main():
                          "stream: 200M pairs streamed from pinned host memory in 8M-pair chunks; "
                          "filters also times MAGNET; partitioned: SneakySnake on sub-mazes of t = 5, 10, 25, 50 columns vs the whole maze "
                          "at E = 0, 5, 10, 25; verify: banded edit distance of the pairs SneakySnake accepts "
-                         "(filter + verify) vs verifying every pair, at E = 5, 10, 25")
+                         "(filter + verify) vs verifying every pair, at E = 5, 10, 25; accuracy: false accept "
+                         "and false reject rates of every filter against the exact banded distance, at E = 0, 5, "
+                         "10, 25")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain copy kernel of known size (counter calibration)")
     ap.add_argument("--calibrate-valu", action="store_true",
@@ -246,7 +249,7 @@ def main():
     if args.workload == "filters":
         filters_workload(args)
         return
-    if args.workload in ("partitioned", "verify"):
+    if args.workload in ("partitioned", "verify", "accuracy"):
         next_workloads(args)
         return
     if args.workload != "fixed250":
@@ -589,6 +592,47 @@ def next_workloads(args):
         ctx.check()
         return sum(per) / len(per)
 
+    if args.workload == "accuracy":
+        # Sec. 3.1.2: a pair is a correct mapping when its edit distance is at
+        # most E; paf_verify gives min(banded distance, E+1) of every pair,
+        # which is the exact verdict.
+        from paper_1910_03936_amd.accuracy import confusion
+        GK, SH = paf.GATEKEEPER, paf.SHOUJI
+        by_E = {}
+        for E in (0, 5, 10, 25):
+            b = dataclasses.replace(base, uniform_E=E, max_E=E)
+            dist_t = torch.empty(n, dtype=torch.int16, device=dev)
+            ver_ms = timed(lambda: ctx.verify(b, dist=dist_t))
+            dist = paf.counts_u16(dist_t).cpu().numpy()
+            runs = {"sneakysnake": (lambda o: ctx.filter(b, SS, out=o), SS, SS)}
+            for t in (5, 10, 25, 50):
+                runs[f"sneakysnake-{t}"] = ((lambda o, t=t: ctx.filter_partitioned(b, t, out=o)), SS, SS)
+            runs["hardware t=8 y=3"] = (lambda o: ctx.filter_partitioned(b, 8, 3, out=o), SS, SS)
+            runs["gatekeeper"] = (lambda o: ctx.filter(b, GK, out=o), GK, GK)
+            runs["shouji"] = (lambda o: ctx.filter(b, SH, out=o), SH, SH)
+            runs["magnet"] = (lambda o: ctx.filter_magnet(b, out=o), SS, SS)
+            row = {"verify_every_pair_ms": round(ver_ms, 4)}
+            for name, (fn, mask, slot) in runs.items():
+                o = ctx.alloc_out(n, mask, dev)
+                ms = timed(lambda: fn(o))
+                acc = paf.accept_bits_to_bool(o[slot][0], n).cpu().numpy()
+                c = confusion(acc, dist, E)
+                row[name] = {"ms": round(ms, 4), "accept_rate": round(float(acc.mean()), 6),
+                             "FAR": round(c["FAR"], 6), "FRR": round(c["FRR"], 6), "FA": c["FA"], "FR": c["FR"],
+                             "correct": c["correct"], "incorrect": c["incorrect"]}
+                del o
+            if row["sneakysnake"]["FR"] != 0:
+                raise AssertionError(f"E={E}: SneakySnake rejected {row['sneakysnake']['FR']} correct pairs")
+            by_E[str(E)] = row
+            log(f"E={E}: correct {row['sneakysnake']['correct']}, " + ", ".join(
+                f"{k} FAR {v['FAR']:.4f} FRR {v['FRR']:.5f}" for k, v in row.items() if isinstance(v, dict)))
+        r = by_E["10"]["sneakysnake"]
+        emit(args, n / (r["ms"] / 1e3), r["ms"],
+             f"{n} pairs, 250 bp, 2-bit packed, 70% unrelated, k~U{{0..40}}; false accept / false reject rates "
+             f"of each filter against the exact banded edit distance (paf_verify); value: SneakySnake at E=10",
+             {"pairs": n, "read_len": 250, "E": [0, 5, 10, 25]}, None, None, {"by_E": by_E})
+        ctx.close()
+        return
     if args.workload == "partitioned":
         by_E = {}
         for E in (0, 5, 10, 25):

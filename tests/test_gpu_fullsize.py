@@ -202,3 +202,46 @@ def test_full_size_verify_survivors(gpu_ctx, fixed250, E):
     acc = paf.accept_bits_to_bool(out[SS][0], n).cpu().numpy()
     assert np.all(acc[d <= E])
     gpu_ctx.check()
+
+
+@pytest.mark.parametrize("E", [0, 5, 10, 25])
+def test_full_size_accuracy(gpu_ctx, fixed250, E):
+    """Confusion counts (Sec. 3.1.2) of every filter against the exact
+    verdict: on every pair from the GPU's banded distances (SneakySnake never
+    rejects a correct pair), and on the subsample the GPU's counts equal the
+    ones the oracle's filters and banded distance give."""
+    from paper_1910_03936_amd.accuracy import confusion
+    b, sub, s = fixed250
+    b.uniform_E = E
+    b.max_E = E
+    n = b.n_pairs
+    dist = paf.counts_u16(gpu_ctx.verify(b)).cpu().numpy()
+    gpu = {"sneakysnake": results(gpu_ctx.filter(b, SS), n)[SS][0]}
+    shared = results(gpu_ctx.filter(b, GK | SH), n)
+    gpu["gatekeeper"], gpu["shouji"] = shared[GK][0], shared[SH][0]
+    for t in (5, 10, 25, 50):
+        gpu[f"sneakysnake-{t}"] = results(gpu_ctx.filter_partitioned(b, t), n)[SS][0]
+    gpu["hardware t=8 y=3"] = results(gpu_ctx.filter_partitioned(b, 8, 3), n)[SS][0]
+    gpu["magnet"] = results(gpu_ctx.filter_magnet(b), n)[SS][0]
+    gpu_ctx.check()
+    whole = confusion(gpu["sneakysnake"], dist, E)
+    assert whole["FR"] == 0 and whole["FRR"] == 0.0, f"E={E}: SneakySnake rejected {whole['FR']} correct pairs"
+    # the subsample, from the oracle alone
+    Es = np.full(s.n, E)
+    correct = oracle.banded_batch(s.reads, s.refs, s.len, Es).astype(np.int64) <= E
+    ref = {"sneakysnake": oracle.filter_batch(s.reads, s.refs, s.len, Es, SS)[SS][0]}
+    o2 = oracle.filter_batch(s.reads, s.refs, s.len, Es, GK | SH)
+    ref["gatekeeper"], ref["shouji"] = o2[GK][0], o2[SH][0]
+    for t in (5, 10, 25, 50):
+        ref[f"sneakysnake-{t}"] = oracle.sneakysnake_t_batch(s.reads, s.refs, s.len, E, t)[0]
+    ref["hardware t=8 y=3"] = oracle.sneakysnake_fpga_batch(s.reads, s.refs, s.len, E, 8, 3)[0]
+    ref["magnet"] = oracle.magnet_batch(s.reads, s.refs, s.len, E)[0]
+    ix = sub.astype(np.int64)
+    for name, acc in gpu.items():
+        got = confusion(acc[ix], dist[ix], E)
+        a = ref[name].astype(bool)
+        want = (int(np.sum(a & correct)), int(np.sum(~a & correct)), int(np.sum(a & ~correct)),
+                int(np.sum(~a & ~correct)))
+        assert (got["TA"], got["FR"], got["FA"], got["TR"]) == want, f"E={E} {name}: {got} vs oracle {want}"
+        if name.startswith("sneakysnake") or name.startswith("hardware"):
+            assert got["FR"] == 0, f"E={E} {name} rejected a correct pair"
