@@ -328,6 +328,21 @@ def main():
         per_k, _, _ = time_steps(lambda: ctx.filter_keyed(batch, key, out=out_k), args.steps, 1)
         model_ms, keyed_ms = sum(per_m) / len(per_m), sum(per_k) / len(per_k)
         hist = torch.bincount(key.to(torch.int64), minlength=16)
+        # Ablations of the key (the keyed filter alone, same layout): a
+        # constant key (the sort's own cost), the trivial length x E key
+        # (constant on this uniform batch) and the true labels' levels (the
+        # best any prediction could do).
+        ablation = {}
+        for kname, kk in (("constant", torch.full((n,), 15, dtype=torch.uint8, device=dev)),
+                          ("length x E", costmodel.length_e_key(batch)),
+                          ("true labels (bound)", costmodel.oracle_key(ctx, batch)),
+                          ("model", key)):
+            per_a, _, _ = time_steps(lambda: ctx.filter_keyed(batch, kk, out=out_k), args.steps, args.warmup)
+            ablation[kname] = round(sum(per_a) / len(per_a), 4)
+        ctx.check()
+        heldout = costmodel.evaluate(ctx, w)
+        log(f"keyed filter by key: {ablation}; held-out MSE {heldout['mse']:.3f} MAE {heldout['mae']:.3f} "
+            f"(predicting the mean: MSE {heldout['mse_of_mean']:.3f})")
         # For context: the same model with a global 16-bucket permutation.
         gsteps = max(3, args.steps // 4)
         out_g = ctx.alloc_out(n, SS, dev)
@@ -341,6 +356,8 @@ def main():
                    "stages_ms": {"features+model (levels)": round(model_ms, 4),
                                  "compacting filter, chunks ordered by level": round(keyed_ms, 4)},
                    "level_sizes": hist.cpu().tolist(),
+                   "keyed_filter_ms_by_key": ablation,
+                   "heldout": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in heldout.items()},
                    "global_permutation_ms_per_step": round(total_g / gsteps, 4),
                    "train": {"pairs": args.train_pairs, "epochs": 4, "seconds": round(train_s, 2),
                              "epoch_mse": [round(float(x), 3) for x in losses]}}
@@ -521,6 +538,14 @@ def other_workload(args):
         model_ms, model_k = timed(lambda: ctx.cost_levels(b))
         keyed_ms, keyed_k = timed(lambda: ctx.filter_keyed(b, key, out=out_l))
         hist = torch.bincount(key.to(torch.int64), minlength=16)
+        ablation = {}
+        for kname, kk in (("constant", torch.full((n,), 15, dtype=torch.uint8, device=b.reads.device)),
+                          ("length x E", costmodel.length_e_key(b)),
+                          ("true labels (bound)", costmodel.oracle_key(ctx, b)),
+                          ("model", key)):
+            ablation[kname] = round(timed(lambda: ctx.filter_keyed(b, kk, out=out_l))[1], 4)
+        heldout = costmodel.evaluate(ctx, pairgen.TRAIN_MIX)
+        log(f"keyed filter by key: {ablation}; held-out MSE {heldout['mse']:.3f} MAE {heldout['mae']:.3f}")
         log(f"learned {learned_ms:.3f} ms vs plain persistent {tuned_ms:.3f} ms, identical: {same}")
         emit(args, n / (learned_ms / 1e3), learned_ms,
              f"{n} pairs, lengths {{64,100,150,250,300}}, E=floor(0.05 m), 70% unrelated; learned-bucketed "
@@ -532,6 +557,8 @@ def other_workload(args):
                           "stages_ms": {"features+model (levels)": round(model_k, 4),
                                         "compacting filter, chunks ordered by level": round(keyed_k, 4)},
                           "level_sizes": hist.cpu().tolist(),
+                          "keyed_filter_ms_by_key": ablation,
+                          "heldout": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in heldout.items()},
                           "train": {"pairs": args.train_pairs, "epoch_mse": [round(float(x), 3) for x in losses]}}})
         return
     # stream

@@ -405,10 +405,16 @@ def _wave_waste(cost: np.ndarray, order: np.ndarray) -> float:
 
 @gpu
 def test_trained_model_groups_pairs_of_like_cost(gpu_ctx):
-    """What the trained network gains over the method without it: ordering
-    held-out pairs by its prediction puts pairs of like SneakySnake cost (the
-    obstacle count of the whole maze, the label) into the same waves, which
-    input order and an untrained network do not."""
+    """What the trained network gains over the method without it, on held-out
+    uneven pairs: (i) as a predictor of the label (SneakySnake's count over
+    the whole maze), its held-out error is far below that of the trivial key,
+    the mean label of the pair's (length, E) class; (ii) ordering the pairs by
+    its prediction puts pairs of like cost into the same waves of 64, cutting
+    the lane time lost to waiting inside a wave (the sum over waves of the
+    largest label minus each label) well below input order and an untrained
+    network.  The (length, E) order is reported beside it: on that lane
+    measure it is better still (measured 83,809 against 95,649 for the model
+    trained here, 801 for the true order), which the design notes record."""
     from paper_1910_03936_amd import costmodel
     from gpu_util import to_device
     w = pairgen.UNEVEN_MIX.with_seed(123)
@@ -417,17 +423,28 @@ def test_trained_model_groups_pairs_of_like_cost(gpu_ctx):
     cost = oracle.filter_batch(p.reads, p.refs, p.len, costmodel.LABEL_E)[oracle.SNEAKYSNAKE][1].astype(np.float64)
     gpu_ctx.mlp_set_params(pairgen.init_mlp_params())
     untrained = gpu_ctx.mlp_predict(b).cpu().numpy()
-    costmodel.train(gpu_ctx, pairgen.UNEVEN_MIX, n=200_000, epochs=3, batch=4096, lr=2e-3)
+    costmodel.train(gpu_ctx, pairgen.UNEVEN_MIX, n=500_000, epochs=4, batch=4096, lr=2e-3)
     trained = gpu_ctx.mlp_predict(b).cpu().numpy()
+    # (i) prediction error against the (length, E) class means of these pairs
+    cls = p.len.astype(np.int64) * 64 + p.E
+    means = {c: cost[cls == c].mean() for c in np.unique(cls)}
+    class_mean = np.array([means[c] for c in cls])
+    mse_model = float(np.mean((trained - cost) ** 2))
+    mse_class = float(np.mean((class_mean - cost) ** 2))
+    # (ii) lane waste of waves of 64 in each order
     plain = _wave_waste(cost, np.arange(p.n))
     best = _wave_waste(cost, np.argsort(cost, kind="stable"))
     by_untrained = _wave_waste(cost, np.argsort(untrained, kind="stable"))
     by_trained = _wave_waste(cost, np.argsort(trained, kind="stable"))
-    print(f"lane waste: input order {plain:.0f}, untrained {by_untrained:.0f}, trained {by_trained:.0f}, "
-          f"sorted by the true cost {best:.0f}")
-    # Measured: input order 131617, untrained 131617 (in both orders every
-    # wave still holds a pair at the label's cap, 32, so both waste the
-    # same), trained 97121, sorted by the true cost 801.
+    by_length_e = _wave_waste(cost, np.argsort(cls, kind="stable"))
+    print(f"MSE: model {mse_model:.2f}, (length, E) class mean {mse_class:.2f}; lane waste: input order {plain:.0f}, "
+          f"untrained {by_untrained:.0f}, trained {by_trained:.0f}, (length, E) {by_length_e:.0f}, "
+          f"true order {best:.0f}")
+    # Measured: MSE 10.4 against 56.7; waste 131,617 / 131,617 / 95,649 /
+    # 83,809 / 801.  The bars leave a margin below those figures: the model
+    # must cut the class-mean error at least in half, and recover at least
+    # 15% of the lane waste of input order (it recovers 27%).
+    assert mse_model < 0.5 * mse_class, (mse_model, mse_class)
     assert by_trained < 0.85 * plain, (by_trained, plain)
     assert by_trained < 0.85 * by_untrained, (by_trained, by_untrained)
     assert best <= by_trained
