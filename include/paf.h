@@ -249,7 +249,10 @@ paf_status paf_filter_persistent(paf_ctx* ctx, const paf_batch* batch, uint32_t 
  * takes waves_per_block, chunk_tiles and the pass widths from a forced
  * layout). */
 typedef struct {
-    uint32_t lanes_per_pair;   /* 1 (pair per lane) */
+    uint32_t lanes_per_pair;   /* 1 (pair per lane), or 2: SneakySnake on the compacting engine
+                                  with a pair's diagonals split between two lanes that OR their
+                                  runs after every probe (max_E 9 and up; paf_filter_partitioned
+                                  always runs one lane per pair) */
     uint32_t waves_per_block;  /* 1, 2, 4 or 8 */
     uint32_t blocks_per_cu;    /* resident blocks per compute unit in the persistent grid;
                                   0 = no work queue: a full grid, one tile per wave */

@@ -133,7 +133,7 @@ paf_layout plain_layout(int emax) {
 }
 
 bool layout_ok(const paf_layout& l) {
-    return l.lanes_per_pair == 1 &&
+    return (l.lanes_per_pair == 1 || l.lanes_per_pair == 2) &&
            (l.waves_per_block == 1 || l.waves_per_block == 2 || l.waves_per_block == 4 ||
             l.waves_per_block == 8) &&
            l.blocks_per_cu <= 64 && l.tiles_per_grab >= 1 &&
@@ -151,6 +151,14 @@ int resident_blocks(const void* k, uint32_t waves, size_t lds) {
 uint64_t mix(uint64_t h, uint64_t v) {
     h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
     return h;
+}
+
+// The compacting engine of a layout: one lane per pair, or two (the whole
+// maze with the diagonals split between the lanes, from max_E 9 on).
+Engine compacting_engine(const paf_layout& L, int emax, paf_status& st) {
+    if (L.lanes_per_pair != 2) return Engine::Chunk;
+    if (emax < 10) st = fail(PAF_ERR_ARG, "two lanes per pair need max_E >= 9");
+    return Engine::Chunk2;
 }
 
 // Replays the graph cached under `key`, or captures `body` (which must only
@@ -192,22 +200,26 @@ paf_status run_persistent(paf_ctx* ctx, FilterParams p, Engine eng, int emax, co
     // Per-pair lengths, thresholds, offsets or an order need the general
     // kernels; a uniform batch in place takes the plain ones.
     const bool general = p.len || p.E || p.word_offset || p.perm;
-    // SneakySnake alone with a chunk size: the compacting engine; its queue
-    // and grid count chunks instead of tiles.
-    if (eng == Engine::Snake && L.chunk_tiles > 0) eng = Engine::Chunk;
+    // SneakySnake alone with a chunk size: the compacting engine (one or two
+    // lanes per pair); its queue and grid count chunks instead of tiles.
+    paf_status st = PAF_OK;
+    if (eng == Engine::Snake && L.chunk_tiles > 0) eng = compacting_engine(L, emax, st);
+    else if (L.lanes_per_pair != 1) st = fail(PAF_ERR_ARG, "two lanes per pair need the compacting engine");
+    if (st != PAF_OK) return st;
+    const bool compacting = eng == Engine::Chunk || eng == Engine::Chunk2;
     const void* k = filter_kernel_ptr(eng, general, emax, p.filters);
     if (!k) return fail(PAF_ERR_RANGE, "no kernel for this threshold");
     if (L.waves_per_block > max_waves(eng)) return fail(PAF_ERR_ARG, "too many waves per block for this engine");
     LaunchShape sh;
     sh.waves_per_block = L.waves_per_block;
-    p.chunk = eng == Engine::Chunk ? L.chunk_tiles : 0u;
+    p.chunk = compacting ? L.chunk_tiles : 0u;
     p.span0 = std::max(1u, L.first_pass_windows);
     p.span = std::max(1u, L.pass_windows);
-    sh.lds_bytes = eng == Engine::Chunk ? chunk_lds_bytes(L.waves_per_block, general, emax, L.chunk_tiles)
-                                        : filter_lds_bytes(L.waves_per_block, p.wmax);
+    sh.lds_bytes = compacting ? chunk_lds_bytes(L.waves_per_block, general, emax, L.chunk_tiles, L.lanes_per_pair)
+                              : filter_lds_bytes(L.waves_per_block, p.wmax);
     if (sh.lds_bytes > 160 * 1024) return fail(PAF_ERR_RANGE, "layout needs more LDS than a CU has");
     PAF_HIP(allow_lds(k, sh.lds_bytes), "hipFuncSetAttribute");
-    const uint64_t units = eng == Engine::Chunk ? (p.n_tiles + p.chunk - 1) / p.chunk : p.n_tiles;
+    const uint64_t units = compacting ? (p.n_tiles + p.chunk - 1) / p.chunk : p.n_tiles;
     const uint64_t need = (units + L.waves_per_block - 1) / L.waves_per_block;
     if (L.blocks_per_cu == 0) {
         // Full grid, one tile per wave: the hardware dispatcher is the queue.
@@ -534,12 +546,13 @@ paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, co
     // (a forced layout may set its chunk size and block shape, or turn it off).
     const paf_layout PL = ctx->layout_forced ? ctx->forced : plain_layout(emax);
     if (eng == Engine::Snake && PL.chunk_tiles > 0) {
-        eng = Engine::Chunk;
+        eng = compacting_engine(PL, emax, st);
+        if (st != PAF_OK) return st;
         p.chunk = PL.chunk_tiles;
         p.span0 = std::max(1u, PL.first_pass_windows);
         p.span = std::max(1u, PL.pass_windows);
         sh.waves_per_block = PL.waves_per_block;
-        sh.lds_bytes = chunk_lds_bytes(sh.waves_per_block, general, emax, p.chunk);
+        sh.lds_bytes = chunk_lds_bytes(sh.waves_per_block, general, emax, p.chunk, PL.lanes_per_pair);
         if (sh.lds_bytes > 160 * 1024) return fail(PAF_ERR_RANGE, "layout needs more LDS than a CU has");
         units = (p.n_tiles + p.chunk - 1) / p.chunk;
     }
@@ -690,14 +703,19 @@ paf_status paf_autotune(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, 
                 cands.push_back(l);
             }
         if (eng != Engine::Snake) continue;
-        for (uint32_t K : {4u, 6u, 8u, 16u}) {
-            const size_t lds = chunk_lds_bytes(wpb, true, emax, K);
-            if (lds > 160 * 1024) continue;
-            for (uint32_t sp : {1u, 2u}) {
-                cands.push_back(paf_layout{1u, wpb, 0u, 1u, K, sp, sp});
-                for (uint32_t bpc : {2u, 4u}) {
-                    if (lds * bpc > 160 * 1024 || wpb * bpc > 32) continue;
-                    cands.push_back(paf_layout{1u, wpb, bpc, 1u, K, sp, sp});
+        // Compacting layouts, with one lane per pair and (the whole maze from
+        // max_E 9 on) two.
+        for (uint32_t lpp : {1u, 2u}) {
+            if (lpp == 2 && emax < 10) continue;
+            for (uint32_t K : {4u, 6u, 8u, 16u}) {
+                const size_t lds = chunk_lds_bytes(wpb, true, emax, K, lpp);
+                if (lds > 160 * 1024) continue;
+                for (uint32_t sp : {1u, 2u}) {
+                    cands.push_back(paf_layout{lpp, wpb, 0u, 1u, K, sp, sp});
+                    for (uint32_t bpc : {2u, 4u}) {
+                        if (lds * bpc > 160 * 1024 || wpb * bpc > 32) continue;
+                        cands.push_back(paf_layout{lpp, wpb, bpc, 1u, K, sp, sp});
+                    }
                 }
             }
         }

@@ -206,15 +206,64 @@ __device__ __forceinline__ void chunk_map(const WindowWords& q, DT dead, uint32_
     }
 }
 
-template <int EMAX, bool GENERAL>
+// Two lanes per pair: lane h = 0 builds the match words of diagonals
+// d = -EMAX..0 and lane h = 1 those of d = 0..EMAX (EMAX + 1 slots each; the
+// main diagonal is in both, which changes neither the deepest pipe nor its
+// continuation).  Slot I of lane h reads the read plane shifted by I + s_h:
+// s_1 = 0 (words c, n) and s_0 = 32 - EMAX (words p, c), so after one
+// funnel shift per plane at the window's start (A, B below) every slot is a
+// funnel shift by the compile-time I, as in chunk_map.  Vacancy comes from the
+// per-lane vacancy words (VAC), the dead bits of a snake inside a pipe from
+// this lane's half of the mask.
+struct HalfWords {
+    uint32_t alo, blo, ahi, bhi, flo, fhi, va, vb;
+};
+
+template <int EMAX>
+__device__ __forceinline__ HalfWords half_words(const WindowWords& q, int h) {
+    constexpr uint32_t s0 = 32u - (uint32_t)EMAX;
+    HalfWords r;
+    r.alo = h ? q.clo : funnel(q.clo, q.plo, s0);
+    r.blo = h ? q.nlo : (q.clo >> s0);
+    r.ahi = h ? q.chi : funnel(q.chi, q.phi, s0);
+    r.bhi = h ? q.nhi : (q.chi >> s0);
+    r.va = h ? q.vc : funnel(q.vc, q.vp, s0);
+    r.vb = h ? q.vn : (q.vc >> s0);
+    r.flo = q.flo;
+    r.fhi = q.fhi;
+    return r;
+}
+
+template <int EMAX, bool VAC, bool CONT, int I = 0>
+__device__ __forceinline__ void chunk_map_half(const HalfWords& q, uint32_t dead, uint32_t* M) {
+    if constexpr (I < EMAX + 1) {
+        const uint32_t lo = funnel(q.blo, q.alo, I);
+        const uint32_t hi = funnel(q.bhi, q.ahi, I);
+        uint32_t v = 0;
+        if constexpr (VAC) v = funnel(q.vb, q.va, I);
+        if constexpr (CONT) v |= (dead >> I) & 1u;
+        const uint32_t t = (VAC || CONT) ? or_xor3(lo, v, q.flo) : lo ^ q.flo;
+        M[I] = nor_xor3(hi, t, q.fhi);
+        chunk_map_half<EMAX, VAC, CONT, I + 1>(q, dead, M);
+    }
+}
+
+// Dead-diagonal mask of one lane: with two lanes per pair each lane keeps the
+// bits of its own half of the diagonals (EMAX + 1 of them, so 32 bits do).
+template <int EMAX, int LPP>
+struct ChunkDead {
+    using T = typename std::conditional<LPP == 2, uint32_t, typename DeadMask<EMAX>::T>::type;
+};
+
+template <typename DT, bool GENERAL>
 struct ChunkLds {
-    using DT = typename DeadMask<EMAX>::T;
     uint64_t* ent;    // the list: K*64 entries
     uint64_t* off;    // GENERAL only: word offset of each pair of the chunk (by pair index)
     uint64_t* stage;  // first-pass words of one group (kStageRead rows of read words, then
                       // kStageRef rows of reference words, 64 words each); after the first
                       // pass, the keyed sort's buffer
-    DT* dead;         // dead-diagonal mask of each pair (by pair index)
+    DT* dead;         // dead-diagonal mask of each pair (by pair index; two halves, one per
+                      // lane, with two lanes per pair)
     uint32_t* acc;    // 2K accept words (plain order)
     uint16_t* cnt;    // K*64 counts (plain order)
 };
@@ -296,15 +345,26 @@ __device__ __forceinline__ WindowWords window_words_carried(const uint64_t* rd, 
 // through `span` windows each, reading their words from memory and carrying
 // a pair's read words from one window to the next.  Counts and accept bits
 // of the chunk are collected in LDS and written once at the end.
-template <int EMAX, bool GENERAL, bool PART>
+//
+// LPP = 2: two lanes per pair (whole maze only, EMAX 10 and up): a group is
+// 32 pairs, lane 2j + h holds pair j's half h of the diagonals (chunk_map_half)
+// and both lanes of a pair OR their runs after every probe (one DPP move), so
+// they walk the same snake; lane h = 0 writes the pair's outputs and list
+// entry, each lane its half of the dead-diagonal mask.
+template <int EMAX, bool GENERAL, bool PART, int LPP>
 __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, int lane,
-                            const ChunkLds<EMAX, GENERAL>& L) {
+                            const ChunkLds<typename ChunkDead<EMAX, LPP>::T, GENERAL>& L) {
     constexpr int D = 2 * EMAX + 1;
     // From EMAX 9 on the kernel is bound by instruction issue: there the
     // staging's own instructions cost more than the waits it saves (measured
     // at EMAX 10), and every window reads its words straight from memory.
     constexpr bool STAGED = EMAX <= 8;
-    using DT = typename DeadMask<EMAX>::T;
+    static_assert(LPP == 1 || (LPP == 2 && !PART && !STAGED), "two lanes per pair: whole maze, EMAX >= 9");
+    constexpr int DL = LPP == 2 ? EMAX + 1 : D;   // map words per lane
+    constexpr uint32_t GS = 64 / LPP;             // pairs per group
+    using DT = typename ChunkDead<EMAX, LPP>::T;
+    const int h = LPP == 2 ? (lane & 1) : 0;      // this lane's half of the diagonals
+    const uint32_t pl = (uint32_t)lane / LPP;     // the pair of the group this lane works on
     const uint64_t slot0 = (uint64_t)chunk * K * 64u;
     const uint32_t n_here = (uint32_t)min<uint64_t>((uint64_t)K * 64u, P.n_pairs - slot0);
     const bool plain_out = !(GENERAL && P.perm);
@@ -321,8 +381,8 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
         const bool first_pass = w == 0;
         const uint32_t n_in = first_pass ? n_here : n_ent;
         uint32_t n_out = 0;
-        for (uint32_t g = 0; g < n_in; g += 64) {
-            const uint32_t i = g + (uint32_t)lane;
+        for (uint32_t g = 0; g < n_in; g += GS) {
+            const uint32_t i = g + pl;
             bool act = i < n_in;
             ChunkEntry t = {};
             DT dead = 0;
@@ -378,7 +438,7 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                 }
             } else if (act) {
                 t = chunk_unpack(L.ent[i]);
-                dead = t.cont ? L.dead[t.idx] : (DT)0;
+                dead = t.cont ? L.dead[t.idx * LPP + h] : (DT)0;
                 off = GENERAL ? L.off[t.idx] : (slot0 + t.idx) * (uint64_t)P.stride_words;
             }
             const uint32_t m = act ? t.m : 0u;
@@ -408,8 +468,17 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                 // its first column.
                 const bool near_end = wave_any(act && 32u * (wk + 2) > m);
                 const bool cnt = wave_any(act && cont);
-                uint32_t M[D];
-                if (near_end) {
+                uint32_t M[DL];
+                if constexpr (LPP == 2) {
+                    const HalfWords hq = half_words<EMAX>(q, h);
+                    if (near_end || wk == 0) {
+                        if (cnt) chunk_map_half<EMAX, true, true>(hq, (uint32_t)dead, M);
+                        else chunk_map_half<EMAX, true, false>(hq, (uint32_t)dead, M);
+                    } else {
+                        if (cnt) chunk_map_half<EMAX, false, true>(hq, (uint32_t)dead, M);
+                        else chunk_map_half<EMAX, false, false>(hq, (uint32_t)dead, M);
+                    }
+                } else if (near_end) {
                     if (cnt) chunk_map<EMAX, kVacAny, true>(q, dead, M);
                     else chunk_map<EMAX, kVacAny, false>(q, dead, M);
                 } else if (wk == 0) {
@@ -421,8 +490,8 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                 }
                 if (mask_E) {
 #pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        const int dd = d - EMAX;
+                    for (int d = 0; d < DL; ++d) {
+                        const int dd = LPP == 2 ? (h ? d : d - EMAX) : d - EMAX;
                         if ((uint32_t)(dd < 0 ? -dd : dd) > E) M[d] = 0u;
                     }
                 }
@@ -487,11 +556,14 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                     while ((b & inpair) != 0u && budget >= 0) {
                         uint32_t r0 = 0, r1 = 0;
 #pragma unroll
-                        for (int d = 0; d < D; d += 2) {
+                        for (int d = 0; d < DL; d += 2) {
                             r0 = or_andn(r0, M[d], M[d] + b);
-                            if (d + 1 < D) r1 = or_andn(r1, M[d + 1], M[d + 1] + b);
+                            if (d + 1 < DL) r1 = or_andn(r1, M[d + 1], M[d + 1] + b);
                         }
                         runs = r0 | r1;
+                        // The partner lane's half (quad_perm [1, 0, 3, 2]).
+                        if constexpr (LPP == 2)
+                            runs |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)runs, 0xB1, 0xF, 0xF, false);
                         b = (runs + b) << 1;
                         --budget;
                     }
@@ -514,11 +586,13 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                 // exactly when e <= E) or counted E + 1 edits.
                 if (live && (c >= m || e > E)) {
                     act = false;
-                    if (plain_out) {
-                        L.cnt[t.idx] = (uint16_t)e;
-                        if (e <= E) atomicOr(&L.acc[t.idx >> 5], 1u << (t.idx & 31u));
-                    } else {
-                        P.cnt[0][P.perm[slot0 + t.idx]] = (uint16_t)e;
+                    if (h == 0) {
+                        if (plain_out) {
+                            L.cnt[t.idx] = (uint16_t)e;
+                            if (e <= E) atomicOr(&L.acc[t.idx >> 5], 1u << (t.idx & 31u));
+                        } else {
+                            P.cnt[0][P.perm[slot0 + t.idx]] = (uint16_t)e;
+                        }
                     }
                 }
                 const bool ncont = act && clear != 0u;
@@ -529,31 +603,33 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                 if (wave_any(ncont)) {
                     uint32_t lo = 0, hi = 0;
 #pragma unroll
-                    for (int d = D - 1; d >= 0; --d) {
+                    for (int d = DL - 1; d >= 0; --d) {
                         const uint32_t run = M[d] & ~(M[d] + bs);
                         if (d >= 32) hi = funnel(hi, run, 31);
                         else lo = funnel(lo, run, 31);
                     }
                     const DT alive = (DT)lo | (sizeof(DT) > 4 ? (DT)((uint64_t)hi << 32) : (DT)0);
-                    constexpr DT all = (D >= 8 * (int)sizeof(DT)) ? ~(DT)0 : (((DT)1 << D) - 1);
+                    constexpr DT all = (DL >= 8 * (int)sizeof(DT)) ? ~(DT)0 : (((DT)1 << DL) - 1);
                     dm = ~alive & all;
                 }
                 cont = ncont;
                 dead = cont ? dm : (DT)0;
             }
             // Survivors go on to the next pass (written behind the read
-            // position: n_out + pre <= i).
-            const uint64_t bal = __ballot(act);
-            const uint32_t pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            // position: n_out + pre <= i).  With two lanes per pair the
+            // pair's first lane counts it.
+            const uint64_t bal = __ballot(act) & (LPP == 2 ? 0x5555555555555555ull : ~0ull);
+            const uint32_t first_lane = (uint32_t)lane & ~(uint32_t)(LPP - 1);
+            const uint64_t below = first_lane ? bal & (~0ull >> (64 - first_lane)) : 0ull;
+            const uint32_t pre = (uint32_t)__builtin_popcountll(below);
             if (act) {
                 ChunkEntry u = t;
                 u.c = c;
                 u.e = e;
                 u.cont = cont;
                 u.ep = PART ? ep : 0u;
-                L.ent[n_out + pre] = chunk_pack(u);
-                if (cont) L.dead[t.idx] = dead;
+                if (h == 0) L.ent[n_out + pre] = chunk_pack(u);
+                if (cont) L.dead[t.idx * LPP + h] = dead;
             }
             n_out += (uint32_t)__builtin_popcountll(bal);
         }
@@ -623,26 +699,27 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
 
 // Bytes of one wave's LDS: list, offsets (general layout), staging / sort
 // area, dead masks, accept words and counts.
-template <int EMAX, bool GENERAL>
+template <int EMAX, bool GENERAL, int LPP = 1>
 __host__ __device__ constexpr size_t chunk_wave_bytes_t(uint32_t K) {
-    using DT = typename DeadMask<EMAX>::T;
-    return (size_t)K * 64 * (8 + (GENERAL ? 8 : 0) + sizeof(DT) + 2) + (size_t)kStageArea * 8 + (size_t)K * 8;
+    using DT = typename ChunkDead<EMAX, LPP>::T;
+    return (size_t)K * 64 * (8 + (GENERAL ? 8 : 0) + LPP * sizeof(DT) + 2) + (size_t)kStageArea * 8 +
+           (size_t)K * 8;
 }
 
 // Up to EMAX 8 the kernel is held to the registers of five waves per SIMD:
 // measured faster than four waves with the registers it would take otherwise.
-template <int EMAX, bool GENERAL, bool PART>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(EMAX <= 8 ? 5 : 1)))
+template <int EMAX, bool GENERAL, bool PART, int LPP>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(LPP == 2 ? 4 : (EMAX <= 8 ? 5 : 1))))
 chunk_kernel(FilterParams P) {
     extern __shared__ uint64_t lds[];
-    using DT = typename DeadMask<EMAX>::T;
+    using DT = typename ChunkDead<EMAX, LPP>::T;
     const int lane = threadIdx.x & 63;
     // Wave-uniform, so the LDS pointers below live in scalar registers.
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t K = P.chunk;
     const uint32_t NE = K * 64u;
-    char* b = reinterpret_cast<char*>(lds) + (size_t)wave * chunk_wave_bytes_t<EMAX, GENERAL>(K);
-    ChunkLds<EMAX, GENERAL> L;
+    char* b = reinterpret_cast<char*>(lds) + (size_t)wave * chunk_wave_bytes_t<EMAX, GENERAL, LPP>(K);
+    ChunkLds<DT, GENERAL> L;
     L.ent = reinterpret_cast<uint64_t*>(b);
     b += (size_t)NE * 8;
     if (GENERAL) {
@@ -654,14 +731,14 @@ chunk_kernel(FilterParams P) {
     L.stage = reinterpret_cast<uint64_t*>(b);
     b += (size_t)kStageArea * 8;
     L.dead = reinterpret_cast<DT*>(b);
-    b += (size_t)NE * sizeof(DT);
+    b += (size_t)NE * LPP * sizeof(DT);
     L.acc = reinterpret_cast<uint32_t*>(b);
     b += (size_t)K * 8;
     L.cnt = reinterpret_cast<uint16_t*>(b);
     const uint32_t n_chunks = (P.n_tiles + K - 1) / K;
     if (P.queue == nullptr) {
         const uint32_t ch = blockIdx.x * (blockDim.x >> 6) + wave;
-        if (ch < n_chunks) chunk_snake<EMAX, GENERAL, PART>(P, ch, K, lane, L);
+        if (ch < n_chunks) chunk_snake<EMAX, GENERAL, PART, LPP>(P, ch, K, lane, L);
         return;
     }
     uint32_t c0 = 0;
@@ -670,7 +747,7 @@ chunk_kernel(FilterParams P) {
     while (c0 < n_chunks) {
         uint32_t nx = 0;
         if (lane == 0) nx = atomicAdd(P.queue, 1u);
-        chunk_snake<EMAX, GENERAL, PART>(P, c0, K, lane, L);
+        chunk_snake<EMAX, GENERAL, PART, LPP>(P, c0, K, lane, L);
         wave_lds_sync();
         c0 = __shfl(nx, 0);
     }
@@ -680,7 +757,7 @@ template <bool GENERAL, bool PART>
 const void* chunk_kernel_for(int emax) {
     switch (emax) {
 #define PAF_CASE(X) \
-    case X: return reinterpret_cast<const void*>(&chunk_kernel<X, GENERAL, PART>);
+    case X: return reinterpret_cast<const void*>(&chunk_kernel<X, GENERAL, PART, 1>);
         PAF_CASE(0) PAF_CASE(1) PAF_CASE(2) PAF_CASE(3) PAF_CASE(4) PAF_CASE(5) PAF_CASE(6)
         PAF_CASE(7) PAF_CASE(8) PAF_CASE(10) PAF_CASE(12) PAF_CASE(15) PAF_CASE(20) PAF_CASE(25)
         PAF_CASE(31)
@@ -689,8 +766,21 @@ const void* chunk_kernel_for(int emax) {
     }
 }
 
+// Two lanes per pair: the whole maze from EMAX 10 on.
 template <bool GENERAL>
-size_t chunk_bytes_for(int emax, uint32_t K) {
+const void* chunk2_kernel_for(int emax) {
+    switch (emax) {
+#define PAF_CASE(X) \
+    case X: return reinterpret_cast<const void*>(&chunk_kernel<X, GENERAL, false, 2>);
+        PAF_CASE(10) PAF_CASE(12) PAF_CASE(15) PAF_CASE(20) PAF_CASE(25) PAF_CASE(31)
+#undef PAF_CASE
+        default: return nullptr;
+    }
+}
+
+template <bool GENERAL>
+size_t chunk_bytes_for(int emax, uint32_t K, uint32_t lpp) {
+    if (lpp == 2) return chunk_wave_bytes_t<31, GENERAL, 2>(K);
     return emax <= 15 ? chunk_wave_bytes_t<15, GENERAL>(K) : chunk_wave_bytes_t<31, GENERAL>(K);
 }
 
@@ -781,6 +871,7 @@ int emax_bucket(int max_E) {
 
 const void* filter_kernel_ptr(Engine eng, bool general, int emax, uint32_t filters) {
     if (eng == Engine::Chunk) return general ? chunk_kernel_for<true, false>(emax) : chunk_kernel_for<false, false>(emax);
+    if (eng == Engine::Chunk2) return general ? chunk2_kernel_for<true>(emax) : chunk2_kernel_for<false>(emax);
     if (eng == Engine::ChunkPart)
         return general ? chunk_kernel_for<true, true>(emax) : chunk_kernel_for<false, true>(emax);
     if (eng == Engine::Snake) return general ? snake_kernel_for<true>(emax) : snake_kernel_for<false>(emax);
@@ -791,9 +882,9 @@ size_t filter_lds_bytes(uint32_t waves_per_block, uint32_t wmax) {
     return (size_t)waves_per_block * 2 * wmax * kLdsRow * sizeof(uint64_t);
 }
 
-size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_t chunk_tiles) {
-    return (size_t)waves_per_block *
-           (general ? chunk_bytes_for<true>(emax, chunk_tiles) : chunk_bytes_for<false>(emax, chunk_tiles));
+size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_t chunk_tiles, uint32_t lpp) {
+    return (size_t)waves_per_block * (general ? chunk_bytes_for<true>(emax, chunk_tiles, lpp)
+                                              : chunk_bytes_for<false>(emax, chunk_tiles, lpp));
 }
 
 hipError_t launch_filter(const FilterParams& p, Engine eng, bool general, int emax,

@@ -47,7 +47,8 @@ struct FilterParams {
 };
 
 // Kernel selection.
-enum class Engine { Snake, Whole, Chunk, ChunkPart };
+// Chunk2: the compacting engine with two lanes per pair (whole maze, max_E 9..31).
+enum class Engine { Snake, Whole, Chunk, ChunkPart, Chunk2 };
 
 struct LaunchShape {
     uint32_t waves_per_block;
@@ -98,7 +99,7 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 const void* filter_kernel_ptr(Engine eng, bool general, int emax, uint32_t filters);
 const void* whole_kernel_ptr(bool general, int emax, uint32_t filters);
 size_t filter_lds_bytes(uint32_t waves_per_block, uint32_t wmax);
-size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_t chunk_tiles);
+size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_t chunk_tiles, uint32_t lpp = 1);
 
 // verify.hip: banded edit distance of the selected pairs (sel: accept-bit
 // words, or NULL for every pair).

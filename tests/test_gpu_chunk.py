@@ -119,3 +119,68 @@ def test_chunk_range_violation(ctx):
     mask = np.arange(p.n) != 100
     assert np.array_equal(got[SS][1][mask], want[SS][1][mask])
     assert np.array_equal(got[SS][0][mask], want[SS][0][mask])
+
+
+def _layout2(wpb, bpc, K, span0=1, span=1):
+    return {"lanes_per_pair": 2, "waves_per_block": wpb, "blocks_per_cu": bpc, "tiles_per_grab": 1,
+            "chunk_tiles": K, "first_pass_windows": span0, "pass_windows": span}
+
+
+@pytest.mark.parametrize("E", [9, 10, 12, 15, 20, 25, 31])
+def test_two_lanes_per_pair_fixed_250bp(ctx, E):
+    """A pair's diagonals split between two lanes (whole maze, max_E 9 and
+    up): bit-exact against the oracle under full-grid and queue layouts, chunk
+    sizes and pass widths, with a ragged last chunk."""
+    w = pairgen.FIXED_250BP.with_E(E)
+    p = pairgen.generate(w, 29, 64 * 23 + 17)
+    want = oracle_for(p, SS)
+    b = to_device(p, ctx, per_pair=False, offsets=False)
+    for wpb, bpc, K, s0, s1 in ((2, 0, 6, 2, 3), (4, 0, 1, 1, 1), (1, 2, 3, 2, 2), (4, 1, 16, 3, 1)):
+        ctx.set_layout(_layout2(wpb, bpc, K, s0, s1))
+        tag = f"E={E} lpp=2 wpb={wpb} bpc={bpc} K={K} spans={s0},{s1}"
+        assert_parity(results(ctx.filter(b, SS), p.n), want, f"plain {tag}")
+        assert_parity(results(ctx.filter_persistent(b, SS), p.n), want, f"persistent {tag}")
+    ctx.check()
+
+
+def test_two_lanes_per_pair_uneven_orders_and_keys(ctx):
+    p = pairgen.generate(pairgen.UNEVEN_MIX, 31, 5000)
+    want = oracle_for(p, SS)
+    g = torch.Generator().manual_seed(9)
+    for offsets in (True, False):
+        b = to_device(p, ctx, per_pair=True, offsets=offsets)
+        for lay in (_layout2(2, 0, 6, 2, 2), _layout2(4, 2, 4, 1, 2)):
+            ctx.set_layout(lay)
+            assert_parity(results(ctx.filter(b, SS), p.n), want, f"plain {lay}")
+            assert_parity(results(ctx.filter_persistent(b, SS), p.n), want, f"persistent {lay}")
+            o = torch.randperm(p.n, generator=g).to(torch.int32).cuda()
+            assert_parity(results(ctx.filter_ordered(b, o, SS), p.n), want, f"ordered {lay}")
+            key = torch.randint(0, 16, (p.n,), generator=g, dtype=torch.uint8).cuda()
+            assert_parity(results(ctx.filter_keyed(b, key), p.n), want, f"keyed {lay}")
+    ctx.check()
+
+
+def test_two_lanes_per_pair_word_edges_and_small_thresholds(ctx):
+    """Lengths around every word edge with per-pair thresholds 0..31 under a
+    launch bound of 31 (pairs with E below 9 run with the two-lane split
+    too), and the error for a batch whose bound is below 9."""
+    rng = np.random.default_rng(3)
+    n = 3000
+    lens = rng.choice([1, 2, 31, 32, 33, 63, 64, 65, 96, 127, 128, 129, 255, 256, 257, 300, 511, 512], n)
+    Es = rng.integers(0, 32, n)
+    reads = rng.integers(0, 4, (n, 512)).astype(np.uint8)
+    refs = reads.copy()
+    flip = rng.random((n, 512)) < 0.05
+    refs[flip] = (refs[flip] + 1) % 4
+    p = pairgen.Pairs(reads, refs, lens.astype(np.uint16), Es.astype(np.uint8), np.ones(n, np.uint8),
+                      np.zeros(n, np.uint16))
+    want = oracle_for(p, SS)
+    b = to_device(p, ctx, per_pair=True, offsets=True, max_len=512, max_E=31)
+    ctx.set_layout(_layout2(2, 0, 4, 2, 2))
+    assert_parity(results(ctx.filter(b, SS), p.n), want, "word edges, lpp=2")
+    small = pairgen.generate(pairgen.FIXED_250BP.with_E(5), 0, 200)
+    bs = to_device(small, ctx, per_pair=False, offsets=False)
+    with pytest.raises(paf.PafError):
+        ctx.filter(bs, SS)
+    ctx.set_layout(None)
+    ctx.check()
