@@ -274,6 +274,28 @@ paf_status paf_autotune(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, 
                         void* stream, paf_layout* chosen, float* best_ms, float* default_ms);
 paf_status paf_set_layout(paf_ctx* ctx, const paf_layout* layout); /* NULL = back to autotuned */
 
+/* Checkpoint of the autotuner's cache.  The cache lives in the context and
+ * ends with it; a saved copy spares a later process the timing runs.  One
+ * entry per tuned class (the classes paf_autotune forms: the batch's
+ * ceil(max_len / 32), its max_E rounded up to the next threshold the library
+ * has a kernel for, and the filter mask). */
+typedef struct {
+    uint32_t max_words;  /* 1..16 */
+    uint32_t max_E;      /* one of 0..8, 10, 12, 15, 20, 25, 31 */
+    uint32_t filters;    /* 1..7 */
+    paf_layout layout;
+} paf_tuned_entry;
+
+/* Copies the first min(cap, *count) cached entries into entries [host] (may
+ * be NULL when cap is 0) and sets *count to the number the cache holds. */
+paf_status paf_tuned_export(paf_ctx* ctx, paf_tuned_entry* entries, uint32_t cap, uint32_t* count);
+/* Adds (or replaces) `count` entries [host].  Every entry is checked first
+ * (its class as above, the layout as paf_set_layout checks it, two lanes per
+ * pair only for SneakySnake alone at max_E 10 and up); PAF_ERR_ARG on the
+ * first bad one, and then nothing is added.  A layout whose chunks need more
+ * LDS than a compute unit holds is refused at launch, as a forced one is. */
+paf_status paf_tuned_import(paf_ctx* ctx, const paf_tuned_entry* entries, uint32_t count);
+
 /* Learned cost bucketing.
  * Features of each pair (fp32, 64 per pair, row-major [n][64]): [0] = m/512,
  * [1] = E/32, slot 32+d = fraction of matching map cells over the first
@@ -288,6 +310,16 @@ paf_status paf_features(paf_ctx* ctx, const paf_batch* batch, float* features, v
 #define PAF_MLP_NPARAMS 24961
 paf_status paf_mlp_set_params(paf_ctx* ctx, const float* params /* [host] */);
 paf_status paf_mlp_get_params(paf_ctx* ctx, float* params /* [host] */);
+/* Checkpoint of the model with its optimizer: master weights, Adam's first
+ * and second moments (PAF_MLP_NPARAMS floats each, [host], the layout of
+ * `params`) and the number of Adam steps taken, so that training resumed
+ * from a saved state takes the same steps as training never stopped.
+ * get_state needs a model (PAF_ERR_STATE).  set_state returns PAF_ERR_ARG,
+ * leaving the context as it was, if a value is not finite or a second
+ * moment is negative; it clears the stored gradients (as set_params does). */
+paf_status paf_mlp_get_state(paf_ctx* ctx, float* params, float* adam_m, float* adam_v, uint32_t* step);
+paf_status paf_mlp_set_state(paf_ctx* ctx, const float* params, const float* adam_m, const float* adam_v,
+                             uint32_t step);
 /* Predictions for n feature rows [device] -> out [device] fp32. */
 paf_status paf_mlp_forward(paf_ctx* ctx, const float* features, uint64_t n, float* out, void* stream);
 /* One training step on a minibatch: forward, MSE loss against targets,

@@ -24,16 +24,19 @@ MAX_PART = 65535  # widest sub-maze of paf_filter_partitioned
 MAX_REPL = 31     # most replications (obstacles per sub-maze) of paf_filter_partitioned
 MAGNET_NOALLOC_MAX_PAIRS = 4194304   # largest batch of paf_filter_magnet_noalloc
 MLP_NPARAMS = 24961
+STATE_MAGIC, STATE_VERSION = 0x46415053, 1   # "SPAF": files written by Context.save_state
 
 STATUS = {0: "PAF_OK", 1: "PAF_ERR_ARG", 2: "PAF_ERR_RANGE", 3: "PAF_ERR_DEVICE",
           4: "PAF_ERR_NOMEM", 5: "PAF_ERR_STATE"}
 
 # Every symbol declared in include/paf.h.
 EXPORTS = ("paf_create", "paf_destroy", "paf_last_error", "paf_check", "paf_pack", "paf_pack_host", "paf_pack_ascii",
-           "paf_filter", "paf_filter_partitioned", "paf_filter_magnet", "paf_filter_magnet_noalloc", "paf_verify", "paf_filter_persistent", "paf_autotune", "paf_set_layout", "paf_features",
-           "paf_mlp_set_params", "paf_mlp_get_params", "paf_mlp_forward", "paf_mlp_train_step",
-           "paf_mlp_predict", "paf_mlp_train", "paf_bucket", "paf_filter_ordered", "paf_filter_bucketed",
-           "paf_filter_bucketed_local", "paf_cost_levels", "paf_filter_keyed", "paf_stream_filter")
+           "paf_filter", "paf_filter_partitioned", "paf_filter_magnet", "paf_filter_magnet_noalloc", "paf_verify",
+           "paf_filter_persistent", "paf_autotune", "paf_set_layout", "paf_tuned_export", "paf_tuned_import",
+           "paf_features", "paf_mlp_set_params", "paf_mlp_get_params", "paf_mlp_get_state", "paf_mlp_set_state",
+           "paf_mlp_forward", "paf_mlp_train_step", "paf_mlp_predict", "paf_mlp_train", "paf_bucket",
+           "paf_filter_ordered", "paf_filter_bucketed", "paf_filter_bucketed_local", "paf_cost_levels",
+           "paf_filter_keyed", "paf_stream_filter")
 
 
 class PafError(RuntimeError):
@@ -75,6 +78,11 @@ class Layout(ctypes.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
+class _TunedEntry(ctypes.Structure):
+    _fields_ = [("max_words", ctypes.c_uint32), ("max_E", ctypes.c_uint32), ("filters", ctypes.c_uint32),
+                ("layout", Layout)]
+
+
 _lib = None
 
 
@@ -105,6 +113,10 @@ def load_library(path: str = LIB_PATH):
                           ctypes.POINTER(Layout), ctypes.POINTER(ctypes.c_float),
                           ctypes.POINTER(ctypes.c_float)]),
         "paf_set_layout": ([P, ctypes.POINTER(Layout)]),
+        "paf_tuned_export": ([P, ctypes.POINTER(_TunedEntry), U32, ctypes.POINTER(U32)]),
+        "paf_tuned_import": ([P, ctypes.POINTER(_TunedEntry), U32]),
+        "paf_mlp_get_state": ([P, P, P, P, ctypes.POINTER(U32)]),
+        "paf_mlp_set_state": ([P, P, P, P, U32]),
         "paf_features": ([P, ctypes.POINTER(_Batch), P, P]),
         "paf_mlp_set_params": ([P, P]),
         "paf_mlp_get_params": ([P, P]),
@@ -343,6 +355,83 @@ class Context:
             lay = Layout(**layout)
             _check(self.lib.paf_set_layout(self.h, ctypes.byref(lay)))
 
+    # -- checkpoint / resume -------------------------------------------
+    def tuned_export(self) -> list:
+        """The autotuner's cache: [{"max_words", "max_E", "filters", "layout": {...}}]."""
+        n = ctypes.c_uint32()
+        _check(self.lib.paf_tuned_export(self.h, None, 0, ctypes.byref(n)))
+        arr = (_TunedEntry * max(1, n.value))()
+        _check(self.lib.paf_tuned_export(self.h, arr, n.value, ctypes.byref(n)))
+        return [{"max_words": int(e.max_words), "max_E": int(e.max_E), "filters": int(e.filters),
+                 "layout": e.layout.as_dict()} for e in arr[:n.value]]
+
+    def tuned_import(self, entries: list):
+        arr = (_TunedEntry * max(1, len(entries)))()
+        for i, e in enumerate(entries):
+            arr[i] = _TunedEntry(e["max_words"], e["max_E"], e["filters"], Layout(**e["layout"]))
+        _check(self.lib.paf_tuned_import(self.h, arr, len(entries)))
+
+    def mlp_get_state(self) -> dict:
+        import numpy as np
+        st = {k: np.zeros(MLP_NPARAMS, np.float32) for k in ("params", "adam_m", "adam_v")}
+        step = ctypes.c_uint32()
+        _check(self.lib.paf_mlp_get_state(self.h, *(st[k].ctypes.data_as(ctypes.c_void_p)
+                                                    for k in ("params", "adam_m", "adam_v")), ctypes.byref(step)))
+        st["step"] = int(step.value)
+        return st
+
+    def mlp_set_state(self, st: dict):
+        import numpy as np
+        a = {k: np.ascontiguousarray(np.asarray(st[k], dtype=np.float32)) for k in ("params", "adam_m", "adam_v")}
+        for k, v in a.items():
+            if v.shape != (MLP_NPARAMS,):
+                raise ValueError(f"{k} has shape {v.shape}, expected ({MLP_NPARAMS},)")
+        _check(self.lib.paf_mlp_set_state(self.h, *(a[k].ctypes.data_as(ctypes.c_void_p)
+                                                    for k in ("params", "adam_m", "adam_v")), int(st["step"])))
+
+    def save_state(self, path: str, model: bool = True):
+        """Writes the autotune cache and (if `model` and one is loaded) the cost
+        model with its optimizer state to one .npz file (plain arrays, no
+        pickled objects)."""
+        import numpy as np
+        tuned = self.tuned_export()
+        rows = np.array([[e["max_words"], e["max_E"], e["filters"]] + [e["layout"][f] for f, _ in Layout._fields_]
+                         for e in tuned], dtype=np.uint32).reshape(len(tuned), 3 + len(Layout._fields_))
+        arrays = {"format": np.array([STATE_MAGIC, STATE_VERSION], dtype=np.uint32), "tuned": rows}
+        if model:
+            try:
+                st = self.mlp_get_state()
+            except PafError as e:
+                if e.status != 5:   # PAF_ERR_STATE: no model to save
+                    raise
+            else:
+                arrays.update(mlp_params=st["params"], adam_m=st["adam_m"], adam_v=st["adam_v"],
+                              adam_step=np.array([st["step"]], dtype=np.uint32))
+        with open(path, "wb") as f:
+            np.savez(f, **arrays)
+
+    def load_state(self, path: str) -> dict:
+        """Reads a file written by save_state and applies it (the library checks
+        every value first).  Returns what was loaded: {"tuned": n, "model": bool}."""
+        import numpy as np
+        with np.load(path, allow_pickle=False) as z:
+            fmt = z["format"]
+            if fmt.shape != (2,) or int(fmt[0]) != STATE_MAGIC or int(fmt[1]) != STATE_VERSION:
+                raise ValueError(f"{path}: not a state file of this library (format {fmt.tolist()})")
+            rows = z["tuned"]
+            if rows.ndim != 2 or rows.shape[1] != 3 + len(Layout._fields_):
+                raise ValueError(f"{path}: tuned table has shape {rows.shape}")
+            entries = [{"max_words": int(r[0]), "max_E": int(r[1]), "filters": int(r[2]),
+                        "layout": {f: int(v) for (f, _), v in zip(Layout._fields_, r[3:])}} for r in rows]
+            st = None
+            if "mlp_params" in z.files:
+                st = {"params": z["mlp_params"], "adam_m": z["adam_m"], "adam_v": z["adam_v"],
+                      "step": int(z["adam_step"][0])}
+        self.tuned_import(entries)
+        if st is not None:
+            self.mlp_set_state(st)
+        return {"tuned": len(entries), "model": st is not None}
+
     # -- cost model --------------------------------------------------
     def features(self, batch: Batch, stream=None) -> torch.Tensor:
         f = torch.empty((batch.n_pairs, 64), dtype=torch.float32, device=batch.device)
@@ -451,21 +540,37 @@ class HostBatch:
 
 
 def stream_filter(ctx: Context, hb: HostBatch, chunk_pairs: int, filters: int = SNEAKYSNAKE,
-                  learned: bool = False):
+                  learned: bool = False, first_pair: int = 0, out: dict | None = None):
     """paf_stream_filter: returns ({filter: (accept bit words, counts)} in pinned
-    host tensors, stats dict)."""
+    host tensors, stats dict).
+
+    Resume: the stream's progress is its chunk index, and filtering a chunk
+    again writes the same outputs.  A stream stopped after c chunks resumes
+    with first_pair = c * chunk_pairs and the `out` of the stopped call: only
+    pairs first_pair.. are filtered (their words start after the first
+    first_pair pairs' ceil(len / 32) words) and written into `out`."""
     n = hb.n_pairs
-    out = {}
+    if first_pair < 0 or first_pair > n or first_pair % 64 != 0:
+        raise ValueError(f"first_pair {first_pair} must be a multiple of 64 in [0, {n}]")
+    if out is None:
+        out = {}
+        for f in range(3):
+            if filters & (1 << f):
+                out[1 << f] = (torch.zeros((n + 31) // 32, dtype=torch.int32, pin_memory=True),
+                               torch.zeros(n, dtype=torch.int16, pin_memory=True))
     o = _Out()
     for f in range(3):
         if filters & (1 << f):
-            a = torch.zeros((n + 31) // 32, dtype=torch.int32, pin_memory=True)
-            c = torch.zeros(n, dtype=torch.int16, pin_memory=True)
-            out[1 << f] = (a, c)
-            o.accept_bits[f] = a.data_ptr()
-            o.count[f] = c.data_ptr()
-    b = _HostBatch(hb.reads.data_ptr(), hb.refs.data_ptr(), hb.len.data_ptr(), hb.E.data_ptr(),
-                   hb.max_len, hb.max_E, n)
+            a, c = out[1 << f]
+            if a.numel() * 32 < n or c.numel() < n:
+                raise ValueError("out tensors are smaller than the batch")
+            o.accept_bits[f] = a.data_ptr() + (first_pair // 32) * 4
+            o.count[f] = c.data_ptr() + first_pair * 2
+    if first_pair == n:
+        return out, {"seconds": 0.0, "h2d_bytes": 0.0, "chunks": 0}
+    w0 = int(((hb.len[:first_pair].to(torch.int64) + 31) // 32).sum()) if first_pair else 0
+    b = _HostBatch(hb.reads.data_ptr() + 8 * w0, hb.refs.data_ptr() + 8 * w0, hb.len.data_ptr() + 2 * first_pair,
+                   hb.E.data_ptr() + first_pair, hb.max_len, hb.max_E, n - first_pair)
     st = _StreamStats()
     _check(ctx.lib.paf_stream_filter(ctx.h, ctypes.byref(b), chunk_pairs, filters, int(learned),
                                      ctypes.byref(o), ctypes.byref(st)))

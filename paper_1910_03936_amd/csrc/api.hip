@@ -677,6 +677,47 @@ paf_status paf_set_layout(paf_ctx* ctx, const paf_layout* layout) {
     return PAF_OK;
 }
 
+paf_status paf_tuned_export(paf_ctx* ctx, paf_tuned_entry* entries, uint32_t cap, uint32_t* count) {
+    if (!ctx) return fail(PAF_ERR_ARG, "ctx is NULL");
+    if (!count) return fail(PAF_ERR_ARG, "count is NULL");
+    if (cap > 0 && !entries) return fail(PAF_ERR_ARG, "entries is NULL");
+    uint32_t i = 0;
+    for (const auto& kv : ctx->tuned) {
+        if (i < cap) {
+            entries[i].max_words = (uint32_t)std::get<0>(kv.first);
+            entries[i].max_E = (uint32_t)std::get<1>(kv.first);
+            entries[i].filters = std::get<2>(kv.first);
+            entries[i].layout = kv.second;
+        }
+        ++i;
+    }
+    *count = i;
+    return PAF_OK;
+}
+
+paf_status paf_tuned_import(paf_ctx* ctx, const paf_tuned_entry* entries, uint32_t count) {
+    if (!ctx) return fail(PAF_ERR_ARG, "ctx is NULL");
+    if (count > 0 && !entries) return fail(PAF_ERR_ARG, "entries is NULL");
+    // Every entry is checked before any is taken, so a bad file changes nothing.
+    for (uint32_t i = 0; i < count; ++i) {
+        const paf_tuned_entry& t = entries[i];
+        if (t.max_words < 1 || t.max_words > (PAF_MAX_LEN + 31) / 32)
+            return fail(PAF_ERR_ARG, "tuned entry: max_words outside 1..16");
+        if (t.max_E > PAF_MAX_E || emax_bucket((int)t.max_E) != (int)t.max_E)
+            return fail(PAF_ERR_ARG, "tuned entry: max_E is not a threshold class of the library");
+        if (t.filters < 1 || t.filters > 7u)
+            return fail(PAF_ERR_ARG, "tuned entry: filters outside 1..7");
+        if (!layout_ok(t.layout)) return fail(PAF_ERR_ARG, "tuned entry: unsupported layout");
+        if (t.layout.lanes_per_pair == 2 && (t.max_E < 10 || t.filters != PAF_SNEAKYSNAKE))
+            return fail(PAF_ERR_ARG, "tuned entry: two lanes per pair need SneakySnake alone and max_E >= 9");
+    }
+    for (uint32_t i = 0; i < count; ++i) {
+        const paf_tuned_entry& t = entries[i];
+        ctx->tuned[std::make_tuple((int)t.max_words, (int)t.max_E, t.filters)] = t.layout;
+    }
+    return PAF_OK;
+}
+
 paf_status paf_autotune(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, const paf_out* out,
                         void* stream, paf_layout* chosen, float* best_ms, float* default_ms) {
     FilterParams p;

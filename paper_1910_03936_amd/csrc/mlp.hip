@@ -10,6 +10,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstdint>
 #include <vector>
 
 #include "paf_internal.h"
@@ -1081,6 +1083,40 @@ paf_status paf_mlp_get_params(paf_ctx* ctx, float* params) {
     PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     PAF_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
     PAF_HIP(hipMemcpy(params, ctx->mlp.master, PAF_MLP_NPARAMS * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    return PAF_OK;
+}
+
+paf_status paf_mlp_get_state(paf_ctx* ctx, float* params, float* adam_m, float* adam_v, uint32_t* step) {
+    paf_status st = need_model(ctx);
+    if (st != PAF_OK) return st;
+    if (!params || !adam_m || !adam_v || !step) return fail(PAF_ERR_ARG, "state pointer is NULL");
+    PAF_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    PAF_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    const MlpDev& m = ctx->mlp;
+    PAF_HIP(hipMemcpy(params, m.master, PAF_MLP_NPARAMS * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    PAF_HIP(hipMemcpy(adam_m, m.adam_m, PAF_MLP_NPARAMS * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    PAF_HIP(hipMemcpy(adam_v, m.adam_v, PAF_MLP_NPARAMS * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    *step = (uint32_t)m.step;
+    return PAF_OK;
+}
+
+paf_status paf_mlp_set_state(paf_ctx* ctx, const float* params, const float* adam_m, const float* adam_v,
+                             uint32_t step) {
+    if (!ctx) return fail(PAF_ERR_ARG, "ctx is NULL");
+    if (!params || !adam_m || !adam_v) return fail(PAF_ERR_ARG, "state pointer is NULL");
+    if (step > (uint32_t)INT32_MAX) return fail(PAF_ERR_ARG, "step out of range");
+    // Adam's second moment is a running mean of squares: a negative or
+    // non-finite entry cannot come from training and would poison the update.
+    for (uint32_t i = 0; i < PAF_MLP_NPARAMS; ++i)
+        if (!std::isfinite(params[i]) || !std::isfinite(adam_m[i]) || !(adam_v[i] >= 0.0f) ||
+            !std::isfinite(adam_v[i]))
+            return fail(PAF_ERR_ARG, "model state holds a non-finite value or a negative second moment");
+    paf_status st = paf_mlp_set_params(ctx, params);
+    if (st != PAF_OK) return st;
+    MlpDev& m = ctx->mlp;
+    PAF_HIP(hipMemcpy(m.adam_m, adam_m, PAF_MLP_NPARAMS * 4, hipMemcpyHostToDevice), "hipMemcpy");
+    PAF_HIP(hipMemcpy(m.adam_v, adam_v, PAF_MLP_NPARAMS * 4, hipMemcpyHostToDevice), "hipMemcpy");
+    m.step = (int)step;
     return PAF_OK;
 }
 
