@@ -165,6 +165,46 @@ def calibrate_copy(gib=2.0, reps=5):
     print(json.dumps({"copy_bytes_each_way": n * 8, "reps": reps}), flush=True)
 
 
+def hbm_ceiling(gib=4.0, reps=3):
+    """Measured HBM rates: a streaming read of `gib` GiB (libpaf_calib.so's
+    read kernel, 16-byte loads at a grid stride, best over grid sizes) and a
+    device-to-device copy of half that size (torch), each the fastest of
+    `reps` launches timed with HIP events.  Returns GB/s (1e9 bytes)."""
+    import ctypes
+
+    import torch
+
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1910_03936_amd", "libpaf_calib.so"))
+    lib.paf_calib_read.restype = ctypes.c_float
+    lib.paf_calib_read.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
+                                   ctypes.c_void_p]
+    nbytes = int(gib * (1 << 30))
+    src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+    out = torch.zeros(1, dtype=torch.int32, device="cuda")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    read = {}
+    for per_cu in (4, 8, 16, 32):
+        ms = lib.paf_calib_read(ctypes.c_void_p(src.data_ptr()), nbytes // 16, cus * per_cu, reps,
+                                ctypes.c_void_p(out.data_ptr()))
+        if ms <= 0:
+            raise RuntimeError(f"read calibration failed (code {ms})")
+        read[per_cu] = nbytes / (ms / 1e3) / 1e9
+    half = src[: src.numel() // 2]
+    dst = torch.empty_like(half)
+    best = 1e30
+    for r in range(reps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(half)
+        b.record()
+        b.synchronize()
+        if r > 0:
+            best = min(best, a.elapsed_time(b))
+    copy = 2 * half.numel() * 8 / (best / 1e3) / 1e9
+    return {"read_GBps": round(max(read.values()), 1), "read_GBps_by_blocks_per_cu": {k: round(v, 1) for k, v in read.items()},
+            "copy_GBps_read_plus_write": round(copy, 1), "bytes_read": nbytes}
+
+
 CALIB_MIXES = ("v_add_u32", "v_bitop3_b32", "v_bcnt_u32_b32", "probe: v_add_u32 + v_bitop3_b32",
                "v_alignbit_b32", "v_pk_add_u16", "map: v_alignbit_b32 + v_bitop3_b32")
 PROBE_MIX = 3
@@ -223,12 +263,19 @@ def main():
                          "10, 25")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain copy kernel of known size (counter calibration)")
+    ap.add_argument("--calibrate-hbm", action="store_true",
+                    help="only measure the streaming read and copy rates of HBM and print them")
     ap.add_argument("--calibrate-valu", action="store_true",
                     help="only measure the VALU issue rate of known instruction mixes and print it")
     ap.add_argument("--reps", type=int, default=3, help="timed repetitions of each calibration kernel")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.calibrate_hbm:
+        r = hbm_ceiling(reps=args.reps)
+        log(f"HBM streaming read {r['read_GBps']} GB/s, copy {r['copy_GBps_read_plus_write']} GB/s")
+        print(json.dumps(dict(r, published_peak_GBps=HBM_PEAK_GBS)), flush=True)
         return
     if args.calibrate_valu:
         r = valu_ceiling(waves_per_simd=(1, 2, 4, 8), reps=args.reps)

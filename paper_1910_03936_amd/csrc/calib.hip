@@ -1,5 +1,6 @@
-// Issue-rate calibration of the vector ALU on gfx950 (measurement aid; not
-// part of the filter library's interface, built as libpaf_calib.so).
+// Issue-rate calibration of the vector ALU on gfx950, and a streaming read of
+// known size (measurement aids; not part of the filter library's interface,
+// built as libpaf_calib.so).
 //
 // The filter kernels are integer bit work (adds, 3-input logic, funnel
 // shifts, population counts).  Whether a kernel is bound by instruction issue
@@ -79,9 +80,52 @@ const void* kernel_for(int mix) {
     }
 }
 
+// Streaming read: every thread reads 16-byte vectors at a grid stride and
+// folds them into one word, stored only for a value no input can produce.
+__global__ void __launch_bounds__(256) read_kernel(const uint4* __restrict__ src, uint64_t n16, uint32_t seed,
+                                                   uint32_t* out) {
+    uint32_t r = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) {
+        const uint4 v = src[i];
+        r ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    if (r == 0x7fffffffu && seed == 0xffffffffu) out[0] = r;
+}
+
 }  // namespace
 
 extern "C" {
+
+// Reads n16 16-byte vectors from src [device] with `blocks` blocks of 256
+// threads, `reps` times, and returns the fastest time in ms (negative on a
+// HIP error).  `out` [device] is one uint32 the kernel may write.
+float paf_calib_read(const void* src, uint64_t n16, uint32_t blocks, int reps, uint32_t* out) {
+    if (!src || n16 == 0 || blocks == 0 || reps < 1 || !out) return -1.0f;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -2.0f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -2.0f;
+    }
+    float best = 1e30f, rc = 0.0f;
+    for (int r = 0; r <= reps && rc == 0.0f; ++r) {
+        float ms = 0;
+        if (hipEventRecord(e0, nullptr) != hipSuccess) rc = -3.0f;
+        if (rc == 0.0f) {
+            hipLaunchKernelGGL(read_kernel, dim3(blocks), dim3(256), 0, nullptr, (const uint4*)src, n16,
+                               (uint32_t)r + 1u, out);
+            if (hipGetLastError() != hipSuccess) rc = -3.0f;
+        }
+        if (rc == 0.0f && hipEventRecord(e1, nullptr) != hipSuccess) rc = -3.0f;
+        if (rc == 0.0f && hipEventSynchronize(e1) != hipSuccess) rc = -4.0f;
+        if (rc == 0.0f && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = -4.0f;
+        if (rc == 0.0f && r > 0 && ms < best) best = ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc != 0.0f ? rc : best;
+}
 
 // Number of instruction mixes and the VALU instructions per loop turn.
 int paf_calib_mixes(void) { return 7; }

@@ -259,31 +259,33 @@ template <typename DT, bool GENERAL>
 struct ChunkLds {
     uint64_t* ent;    // the list: K*64 entries
     uint64_t* off;    // GENERAL only: word offset of each pair of the chunk (by pair index)
-    uint64_t* stage;  // first-pass words of one group (kStageRead rows of read words, then
-                      // kStageRef rows of reference words, 64 words each); after the first
-                      // pass, the keyed sort's buffer
+    uint64_t* stage;  // the keyed sort's buffer (kStageArea entries)
     DT* dead;         // dead-diagonal mask of each pair (by pair index; two halves, one per
                       // lane, with two lanes per pair)
     uint32_t* acc;    // 2K accept words (plain order)
     uint16_t* cnt;    // K*64 counts (plain order)
 };
 
-// The first pass's windows 0 and 1 read words 0..2 of the read and words 0
-// and 1 of the reference (all inside the rows' first 32-byte sector); those
-// are staged, one LDS row of 64 words per word index.
-constexpr int kStageRead = 3, kStageRef = 2, kStageRow = 64;
-constexpr int kStageArea = (kStageRead + kStageRef) * kStageRow;   // uint64 words per wave
+// Entries the keyed sort of the first pass's survivors can order in LDS.
+constexpr int kStageArea = 320;
 
-// The staged rows of pair `lane` of the group: window k's words (k + 1 <
-// kStageRead).  Rows past a pair's length were staged as zeros.
-__device__ __forceinline__ WindowWords window_words_staged(const uint64_t* st, int lane, int k, int m) {
+// The first pass's windows 0 and 1 read words 0..2 of the read and words 0
+// and 1 of the reference.  Each lane loads its own pair's five at the start
+// of the group, all at once, so the group waits for memory once:
+// w = read words 0..2, then reference words 0 and 1 (zero past the pair).
+__device__ __forceinline__ void first_words(const uint64_t* rd, const uint64_t* rf, uint32_t W, uint64_t (&w)[5]) {
+    w[0] = W > 0u ? rd[0] : 0ull;
+    w[1] = W > 1u ? rd[1] : 0ull;
+    w[2] = W > 2u ? rd[2] : 0ull;
+    w[3] = W > 0u ? rf[0] : 0ull;
+    w[4] = W > 1u ? rf[1] : 0ull;
+}
+
+// Window k (0 or 1) from those words.
+__device__ __forceinline__ WindowWords window_words_first(const uint64_t (&w)[5], int k, int m) {
     WindowWords q;
-    const uint64_t* rd = st;
-    const uint64_t* rf = st + kStageRead * kStageRow;
-    const uint64_t p = k > 0 ? rd[(k - 1) * kStageRow + lane] : 0ull;
-    const uint64_t c = rd[k * kStageRow + lane];
-    const uint64_t n = rd[(k + 1) * kStageRow + lane];
-    const uint64_t f = rf[k * kStageRow + lane];
+    const bool one = k != 0;
+    const uint64_t p = one ? w[0] : 0ull, c = one ? w[1] : w[0], n = one ? w[2] : w[1], f = one ? w[4] : w[3];
     q.plo = (uint32_t)p; q.phi = (uint32_t)(p >> 32);
     q.clo = (uint32_t)c; q.chi = (uint32_t)(c >> 32);
     q.nlo = (uint32_t)n; q.nhi = (uint32_t)(n >> 32);
@@ -336,15 +338,15 @@ __device__ __forceinline__ WindowWords window_words_carried(const uint64_t* rd, 
 // min(y, w - sum x)).
 //
 // Passes.  The first pass takes the chunk's pairs in order, 64 at a time:
-// the words its first two windows read (read words 0..2, reference words 0
-// and 1, inside each row's first 32-byte sector) are loaded for the whole
-// group together, four lanes per sector, into LDS, and the group walks
-// windows [0, span0) from there (later windows of a wider first pass, and
-// every window above EMAX 8, read their words from memory).  The pairs still undecided are appended to the list (in key
-// order when a key is given) and the later passes take the list 64 at a time
-// through `span` windows each, reading their words from memory and carrying
-// a pair's read words from one window to the next.  Counts and accept bits
-// of the chunk are collected in LDS and written once at the end.
+// up to EMAX 10 each lane loads the words of its pair's first two windows at
+// the group's start (first_words), and the group walks windows [0, span0)
+// (later windows of a wider first pass, and every window above EMAX 10, read
+// their words from memory).  The pairs still undecided are appended to the
+// list (in key order when a key is given) and the later passes take the
+// list 64 at a time through `span` windows each, reading their words from
+// memory (up to EMAX 8 carrying a pair's read words from one window to the
+// next).  Counts and accept bits of the chunk are collected in LDS and
+// written once at the end.
 //
 // LPP = 2: two lanes per pair (whole maze only, EMAX 10 and up): a group is
 // 32 pairs, lane 2j + h holds pair j's half h of the diagonals (chunk_map_half)
@@ -355,11 +357,17 @@ template <int EMAX, bool GENERAL, bool PART, int LPP>
 __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, int lane,
                             const ChunkLds<typename ChunkDead<EMAX, LPP>::T, GENERAL>& L) {
     constexpr int D = 2 * EMAX + 1;
-    // From EMAX 9 on the kernel is bound by instruction issue: there the
-    // staging's own instructions cost more than the waits it saves (measured
-    // at EMAX 10), and every window reads its words straight from memory.
-    constexpr bool STAGED = EMAX <= 8;
-    static_assert(LPP == 1 || (LPP == 2 && !PART && !STAGED), "two lanes per pair: whole maze, EMAX >= 9");
+    // Up to EMAX 8 the kernel waits on memory more than it issues: there the
+    // first two windows' words are loaded together at a group's start and a
+    // pair's read words are carried from window to window.  Above, it is
+    // bound by instruction issue and every later window reads its words
+    // straight from memory; the first two windows' words are still loaded
+    // together up to EMAX 10 (measured 2% faster there; from EMAX 12 on the
+    // five extra live words cost a wave per SIMD).
+    constexpr bool FIRST_REGS = LPP == 1 && EMAX <= 10;
+    constexpr bool CARRY = EMAX <= 8;
+    static_assert(LPP == 1 || (LPP == 2 && !PART && !FIRST_REGS && !CARRY),
+                  "two lanes per pair: whole maze, EMAX >= 9");
     constexpr int DL = LPP == 2 ? EMAX + 1 : D;   // map words per lane
     constexpr uint32_t GS = 64 / LPP;             // pairs per group
     using DT = typename ChunkDead<EMAX, LPP>::T;
@@ -387,6 +395,7 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
             ChunkEntry t = {};
             DT dead = 0;
             uint64_t off = 0;
+            uint64_t fw[5] = {};
             if (first_pass) {
                 t.idx = i;
                 t.m = P.uniform_len;
@@ -409,33 +418,8 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                         off = slot * (uint64_t)P.stride_words;
                     }
                 }
-                // Stage the group's first words: lane l takes word l % 4 of
-                // pair l / 4 + 16 r, so four lanes cover one 32-byte sector
-                // (word 3, and the reference's words 2 and 3, are not kept).
-                if constexpr (STAGED) {
-                    wave_lds_sync();
-                    const uint32_t k = (uint32_t)lane & 3u;
-                    const uint32_t Wl = act ? (t.m + 31u) >> 5 : 0u;
-                    const uint32_t offlo = (uint32_t)off, offhi = (uint32_t)(off >> 32);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int j = (lane >> 2) + 16 * r;
-                        uint32_t Wj;
-                        uint64_t o;
-                        if (GENERAL) {
-                            // Each row's length and offset come from the lane that owns it.
-                            Wj = (uint32_t)__shfl((int)Wl, j);
-                            o = ((uint64_t)(uint32_t)__shfl((int)offhi, j) << 32) | (uint32_t)__shfl((int)offlo, j);
-                        } else {
-                            Wj = g + (uint32_t)j < n_in ? (P.uniform_len + 31u) >> 5 : 0u;
-                            o = (slot0 + g + (uint32_t)j) * (uint64_t)P.stride_words;
-                        }
-                        if (k < (uint32_t)kStageRead) L.stage[k * kStageRow + j] = k < Wj ? P.reads[o + k] : 0ull;
-                        if (k < (uint32_t)kStageRef)
-                            L.stage[(kStageRead + k) * kStageRow + j] = k < Wj ? P.refs[o + k] : 0ull;
-                    }
-                    wave_lds_sync();
-                }
+                if constexpr (FIRST_REGS)
+                    first_words(P.reads + off, P.refs + off, act ? (t.m + 31u) >> 5 : 0u, fw);
             } else if (act) {
                 t = chunk_unpack(L.ent[i]);
                 dead = t.cont ? L.dead[t.idx * LPP + h] : (DT)0;
@@ -454,11 +438,11 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
             Carry cy = {0ull, 0ull};
             for (uint32_t wk = w; wk < w + span && wave_any(act); ++wk) {
                 WindowWords q;
-                if constexpr (STAGED) {
-                    q = (first_pass && wk + 1u < (uint32_t)kStageRead)
-                        ? window_words_staged(L.stage, lane, (int)wk, (int)m)
-                        : window_words_carried(P.reads + off, P.refs + off, (int)wk, act ? W : 0, (int)m,
-                                               first_pass ? wk + 1u == (uint32_t)kStageRead : wk == w, cy);
+                if (FIRST_REGS && first_pass && wk < 2u) {
+                    q = window_words_first(fw, (int)wk, (int)m);
+                } else if constexpr (CARRY) {
+                    q = window_words_carried(P.reads + off, P.refs + off, (int)wk, act ? W : 0, (int)m,
+                                             wk == (first_pass && FIRST_REGS ? 2u : w), cy);
                 } else {
                     q = window_words_direct(P.reads + off, P.refs + off, (int)wk, act ? W : 0, (int)m);
                 }
