@@ -141,16 +141,18 @@ paf_status paf_pack_ascii(const char* seqs, uint32_t row_stride, const uint16_t*
                           const uint64_t* word_offset, uint32_t stride_words, uint64_t n, uint64_t* words,
                           int threads);
 
-/* Plain batched filter.  For every pair: stage its words,
+/* Plain batched filter.  For every pair: load its words,
  * build the 2E+1 diagonal match bit-vectors (neighbourhood map, Eq. 6.1 /
  * unweighted maze, Eq. 8.2) and run the requested decision stages on them:
  * SneakySnake's greedy traversal (Ch. 8, Sec. 8.4), GateKeeper's Hamming
  * fast path plus amended shifted masks (Ch. 5, Sec. 5.2) and Shouji's
  * sliding-window search (Ch. 6, Sec. 6.2).  filters: mask of PAF_* bits.
  * SneakySnake alone runs on the compacting engine (see paf_layout's
- * chunk_tiles; 2 waves per block, a first pass of 2 windows, then chunks of 4
- * tiles and later passes of 2 windows up to max_E 8, 6 tiles and 3 windows
- * up to 15, 6 and 2 above; unless a layout was forced with paf_set_layout,
+ * chunk_tiles; a first pass of 2 windows, then: up to max_E 3, 4 waves per
+ * block, chunks of 4 tiles and later passes of 3 windows; 4..6: 2 waves, 4
+ * tiles, 3 windows; 7..8: 2 waves, 6 tiles, 2 windows; 9..15: 2 waves, 6
+ * tiles, 3 windows; above: 2 waves, 6 tiles, 2 windows; unless a layout was
+ * forced with paf_set_layout,
  * whose waves_per_block, chunk_tiles and pass widths then apply here too;
  * chunk_tiles = 0 selects the per-tile engine).  Several stages share one
  * map and one launch up to max_E 7; from max_E 8 SneakySnake runs as above in a launch of its own,

@@ -122,12 +122,15 @@ paf_layout default_layout() {
 }
 
 // Launch shape of paf_filter's SneakySnake-only launch (measured best on
-// 10M pairs of 250 bp): two-wave blocks and a two-window first pass; up to
-// max_E 8, chunks of 4 tiles (the kernel runs five waves per SIMD, so a
-// wave's LDS must stay under 8 KB) and two-window later passes; from 9 to
-// 15, chunks of 6 tiles and three-window later passes; above, 6 and two.
+// 10M pairs of 250 bp, full grid, two-window first pass): up to max_E 3,
+// four-wave blocks and chunks of 4 tiles; 4 to 6, two-wave blocks and chunks
+// of 4; 7 and 8, chunks of 6 (the kernel runs five waves per SIMD up to 8,
+// so a wave's LDS must stay under 8 KB); later passes of three windows, but
+// two at 7 and 8 and above 15.
 paf_layout plain_layout(int emax) {
-    if (emax <= 8) return paf_layout{1u, 2u, 0u, 1u, 4u, 2u, 2u};
+    if (emax <= 3) return paf_layout{1u, 4u, 0u, 1u, 4u, 2u, 3u};
+    if (emax <= 6) return paf_layout{1u, 2u, 0u, 1u, 4u, 2u, 3u};
+    if (emax <= 8) return paf_layout{1u, 2u, 0u, 1u, 6u, 2u, 2u};
     if (emax <= 15) return paf_layout{1u, 2u, 0u, 1u, 6u, 2u, 3u};
     return paf_layout{1u, 2u, 0u, 1u, 6u, 2u, 2u};
 }
@@ -215,7 +218,8 @@ paf_status run_persistent(paf_ctx* ctx, FilterParams p, Engine eng, int emax, co
     p.chunk = compacting ? L.chunk_tiles : 0u;
     p.span0 = std::max(1u, L.first_pass_windows);
     p.span = std::max(1u, L.pass_windows);
-    sh.lds_bytes = compacting ? chunk_lds_bytes(L.waves_per_block, general, emax, L.chunk_tiles, L.lanes_per_pair)
+    sh.lds_bytes = compacting ? chunk_lds_bytes(L.waves_per_block, general, emax, L.chunk_tiles, L.lanes_per_pair,
+                                                p.order_key != nullptr)
                               : filter_lds_bytes(L.waves_per_block, p.wmax);
     if (sh.lds_bytes > 160 * 1024) return fail(PAF_ERR_RANGE, "layout needs more LDS than a CU has");
     PAF_HIP(allow_lds(k, sh.lds_bytes), "hipFuncSetAttribute");
@@ -552,7 +556,7 @@ paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, co
         p.span0 = std::max(1u, PL.first_pass_windows);
         p.span = std::max(1u, PL.pass_windows);
         sh.waves_per_block = PL.waves_per_block;
-        sh.lds_bytes = chunk_lds_bytes(sh.waves_per_block, general, emax, p.chunk, PL.lanes_per_pair);
+        sh.lds_bytes = chunk_lds_bytes(sh.waves_per_block, general, emax, p.chunk, PL.lanes_per_pair, false);
         if (sh.lds_bytes > 160 * 1024) return fail(PAF_ERR_RANGE, "layout needs more LDS than a CU has");
         units = (p.n_tiles + p.chunk - 1) / p.chunk;
     }
@@ -586,7 +590,7 @@ paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t
     p.span = std::max(1u, PL.pass_windows);
     LaunchShape sh;
     sh.waves_per_block = PL.waves_per_block;
-    sh.lds_bytes = chunk_lds_bytes(sh.waves_per_block, general, emax, p.chunk);
+    sh.lds_bytes = chunk_lds_bytes(sh.waves_per_block, general, emax, p.chunk, 1, false);
     if (sh.lds_bytes > 160 * 1024) return fail(PAF_ERR_RANGE, "layout needs more LDS than a CU has");
     const uint64_t units = (p.n_tiles + p.chunk - 1) / p.chunk;
     sh.blocks = (uint32_t)((units + sh.waves_per_block - 1) / sh.waves_per_block);
@@ -749,7 +753,8 @@ paf_status paf_autotune(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, 
         for (uint32_t lpp : {1u, 2u}) {
             if (lpp == 2 && emax < 10) continue;
             for (uint32_t K : {4u, 6u, 8u, 16u}) {
-                const size_t lds = chunk_lds_bytes(wpb, true, emax, K, lpp);
+                // With the sort buffer: a tuned layout also serves the keyed launches.
+                const size_t lds = chunk_lds_bytes(wpb, true, emax, K, lpp, true);
                 if (lds > 160 * 1024) continue;
                 for (uint32_t sp : {1u, 2u}) {
                     cands.push_back(paf_layout{lpp, wpb, 0u, 1u, K, sp, sp});

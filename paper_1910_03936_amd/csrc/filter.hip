@@ -684,9 +684,9 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
 // Bytes of one wave's LDS: list, offsets (general layout), staging / sort
 // area, dead masks, accept words and counts.
 template <int EMAX, bool GENERAL, int LPP = 1>
-__host__ __device__ constexpr size_t chunk_wave_bytes_t(uint32_t K) {
+__host__ __device__ constexpr size_t chunk_wave_bytes_t(uint32_t K, bool keyed) {
     using DT = typename ChunkDead<EMAX, LPP>::T;
-    return (size_t)K * 64 * (8 + (GENERAL ? 8 : 0) + LPP * sizeof(DT) + 2) + (size_t)kStageArea * 8 +
+    return (size_t)K * 64 * (8 + (GENERAL ? 8 : 0) + LPP * sizeof(DT) + 2) + (keyed ? (size_t)kStageArea * 8 : 0) +
            (size_t)K * 8;
 }
 
@@ -702,7 +702,10 @@ chunk_kernel(FilterParams P) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t K = P.chunk;
     const uint32_t NE = K * 64u;
-    char* b = reinterpret_cast<char*>(lds) + (size_t)wave * chunk_wave_bytes_t<EMAX, GENERAL, LPP>(K);
+    // The sort buffer exists only in keyed launches (the others get the LDS
+    // back as occupancy).
+    const bool keyed = P.order_key != nullptr;
+    char* b = reinterpret_cast<char*>(lds) + (size_t)wave * chunk_wave_bytes_t<EMAX, GENERAL, LPP>(K, keyed);
     ChunkLds<DT, GENERAL> L;
     L.ent = reinterpret_cast<uint64_t*>(b);
     b += (size_t)NE * 8;
@@ -712,8 +715,8 @@ chunk_kernel(FilterParams P) {
     } else {
         L.off = nullptr;
     }
-    L.stage = reinterpret_cast<uint64_t*>(b);
-    b += (size_t)kStageArea * 8;
+    L.stage = keyed ? reinterpret_cast<uint64_t*>(b) : nullptr;
+    b += keyed ? (size_t)kStageArea * 8 : 0;
     L.dead = reinterpret_cast<DT*>(b);
     b += (size_t)NE * LPP * sizeof(DT);
     L.acc = reinterpret_cast<uint32_t*>(b);
@@ -763,9 +766,9 @@ const void* chunk2_kernel_for(int emax) {
 }
 
 template <bool GENERAL>
-size_t chunk_bytes_for(int emax, uint32_t K, uint32_t lpp) {
-    if (lpp == 2) return chunk_wave_bytes_t<31, GENERAL, 2>(K);
-    return emax <= 15 ? chunk_wave_bytes_t<15, GENERAL>(K) : chunk_wave_bytes_t<31, GENERAL>(K);
+size_t chunk_bytes_for(int emax, uint32_t K, uint32_t lpp, bool keyed) {
+    if (lpp == 2) return chunk_wave_bytes_t<31, GENERAL, 2>(K, keyed);
+    return emax <= 15 ? chunk_wave_bytes_t<15, GENERAL>(K, keyed) : chunk_wave_bytes_t<31, GENERAL>(K, keyed);
 }
 
 template <int EMAX, bool GENERAL>
@@ -866,9 +869,10 @@ size_t filter_lds_bytes(uint32_t waves_per_block, uint32_t wmax) {
     return (size_t)waves_per_block * 2 * wmax * kLdsRow * sizeof(uint64_t);
 }
 
-size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_t chunk_tiles, uint32_t lpp) {
-    return (size_t)waves_per_block * (general ? chunk_bytes_for<true>(emax, chunk_tiles, lpp)
-                                              : chunk_bytes_for<false>(emax, chunk_tiles, lpp));
+size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_t chunk_tiles, uint32_t lpp,
+                       bool keyed) {
+    return (size_t)waves_per_block * (general ? chunk_bytes_for<true>(emax, chunk_tiles, lpp, keyed)
+                                              : chunk_bytes_for<false>(emax, chunk_tiles, lpp, keyed));
 }
 
 hipError_t launch_filter(const FilterParams& p, Engine eng, bool general, int emax,
