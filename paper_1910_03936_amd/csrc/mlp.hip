@@ -141,9 +141,22 @@ __device__ __forceinline__ void store_fractions(const float* v, uint32_t E, bool
     }
 }
 
+// Which pairs go through the model when only the compacting filter's
+// in-chunk order needs their level.  That order is read only for the pairs
+// a chunk still holds after its first pass (the first 64 columns), and a
+// pair survives that pass only if some diagonal inside its threshold is
+// mostly free there.  So the model runs on the pairs with a diagonal |d| <= E
+// whose matching cells make up at least 2/5 of the first min(m, 64) columns;
+// the others get the cheapest level without running it.  Integer test on the
+// counts: 5 matches >= 2 columns.
+__device__ __forceinline__ bool model_gate(uint32_t matches, uint32_t cols) {
+    return 5u * matches >= 2u * cols;
+}
+
 template <int EF, bool CK = false>
 __device__ __forceinline__ void pair_features(const uint64_t* rd, const uint64_t* rf, uint32_t m,
-                                              uint32_t E, float* f, bool all_long, bool masked) {
+                                              uint32_t E, float* f, bool all_long, bool masked,
+                                              bool* gate = nullptr) {
     constexpr int D = 2 * EF + 1;
     constexpr int NF = CK ? 32 : 64;
     uint32_t z[D];
@@ -163,6 +176,15 @@ __device__ __forceinline__ void pair_features(const uint64_t* rd, const uint64_t
         // 64 columns: the fraction (64 - blocked) / 64 = 1 - blocked / 64, exact.
 #pragma unroll
         for (int i = 0; i < D; ++i) v[i] = __builtin_fmaf((float)z[i], -1.0f / 64.0f, 1.0f);
+        if (gate) {
+            bool g = false;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const int d = i - EF;
+                g |= (uint32_t)(d < 0 ? -d : d) <= E && model_gate(64u - z[i], 64u);
+            }
+            *gate = g;
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -177,8 +199,29 @@ __device__ __forceinline__ void pair_features(const uint64_t* rd, const uint64_t
         const float rcp = 1.0f / (float)cols;
 #pragma unroll
         for (int i = 0; i < D; ++i) v[i] = (float)z[i] * rcp;
+        if (gate) {
+            bool g = false;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const int d = i - EF;
+                g |= (uint32_t)(d < 0 ? -d : d) <= E && model_gate(z[i], cols);
+            }
+            *gate = g;
+        }
     }
     store_fractions<EF, CK>(v, E, masked, f);
+}
+
+// A feature vector rounded to bf16, eight inputs per 16-byte word.
+template <int NF>
+__device__ __forceinline__ void pack_row(const float* v, uint4 (&row)[NF / 8]) {
+#pragma unroll
+    for (int c = 0; c < NF / 8; ++c) {
+        row[c].x = bf16_bits(v[8 * c + 0]) | ((uint32_t)bf16_bits(v[8 * c + 1]) << 16);
+        row[c].y = bf16_bits(v[8 * c + 2]) | ((uint32_t)bf16_bits(v[8 * c + 3]) << 16);
+        row[c].z = bf16_bits(v[8 * c + 4]) | ((uint32_t)bf16_bits(v[8 * c + 5]) << 16);
+        row[c].w = bf16_bits(v[8 * c + 6]) | ((uint32_t)bf16_bits(v[8 * c + 7]) << 16);
+    }
 }
 
 // Fast path of the compact layout (every read of the wave at least 64 + EF
@@ -215,7 +258,8 @@ __device__ __forceinline__ void blocked_counts(uint32_t plo, uint32_t phi, uint3
 
 template <int EF>
 __device__ __forceinline__ void stage_compact_fast(uint64_t r0, uint64_t r1, uint64_t r2, uint64_t f0,
-                                                   uint64_t f1, uint32_t m, uint32_t E, uint16_t* row) {
+                                                   uint64_t f1, uint32_t m, uint32_t E, uint4 (&row)[4],
+                                                   bool& gate) {
     constexpr int D = 2 * EF + 1;
     uint32_t z[D];
 #pragma unroll
@@ -231,15 +275,12 @@ __device__ __forceinline__ void stage_compact_fast(uint64_t r0, uint64_t r1, uin
     for (int i = 0; i < D; ++i) v[2 + i] = __builtin_fmaf((float)z[i], -1.0f / 64.0f, 1.0f);
 #pragma unroll
     for (int i = D + 2; i < 32; ++i) v[i] = 0.0f;
+    pack_row<32>(v, row);
+    // Every lane of the wave has E >= EF here: all diagonals are inside it.
+    bool g = false;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        uint4 u;
-        u.x = bf16_bits(v[8 * c + 0]) | ((uint32_t)bf16_bits(v[8 * c + 1]) << 16);
-        u.y = bf16_bits(v[8 * c + 2]) | ((uint32_t)bf16_bits(v[8 * c + 3]) << 16);
-        u.z = bf16_bits(v[8 * c + 4]) | ((uint32_t)bf16_bits(v[8 * c + 5]) << 16);
-        u.w = bf16_bits(v[8 * c + 6]) | ((uint32_t)bf16_bits(v[8 * c + 7]) << 16);
-        *reinterpret_cast<uint4*>(&row[8 * c]) = u;
-    }
+    for (int i = 0; i < D; ++i) g |= model_gate(64u - z[i], 64u);
+    gate = g;
 }
 
 struct PairRef {
@@ -336,6 +377,7 @@ struct KeyParams {
     float* pred;       // optional
     uint8_t* bucket;   // optional
     uint32_t chunk_key;  // bucket = 15 - chunk_level (in-chunk order) instead of 15 - cost_bucket
+    uint32_t gate;       // with chunk_key and no pred: only pairs that pass model_gate run the model
 };
 
 constexpr int kKeyWaves = 8;  // waves per block of the fused kernel (weights shared in LDS)
@@ -365,10 +407,10 @@ __device__ __forceinline__ FeatWords feat_words(const FilterParams& P, uint64_t 
 
 template <int EF, bool CK>
 __device__ __forceinline__ void features_from_words(const FeatWords& w, float* f, bool all_long,
-                                                    bool masked) {
+                                                    bool masked, bool* gate) {
     uint64_t rd[3] = {w.r0, w.r1, w.r2};
     uint64_t rf[2] = {w.f0, w.f1};
-    pair_features<EF, CK>(rd, rf, w.m, w.E, f, all_long, masked);
+    pair_features<EF, CK>(rd, rf, w.m, w.E, f, all_long, masked, gate);
 }
 
 // With at most 14 diagonals per side the non-zero inputs (m/512, E/32 and
@@ -385,7 +427,11 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
     __shared__ __attribute__((aligned(16))) float sB1[kHid];
     __shared__ __attribute__((aligned(16))) float sB2[kHid];
     __shared__ float sW3[kHid];
-    __shared__ __attribute__((aligned(16))) uint16_t sX[kKeyWaves][64][NF + 8];
+    // Gated launches hold up to 127 rows per wave (a partial tile of rows
+    // that passed the gate plus the next tile's).
+    constexpr int ROWS = CK ? 128 : 64;
+    __shared__ __attribute__((aligned(16))) uint16_t sX[kKeyWaves][ROWS][NF + 8];
+    __shared__ uint64_t sIdx[kKeyWaves][CK ? 128 : 1];
     const FilterParams& P = K.P;
     if constexpr (CK) {
         // Fragment order for one k-tile: lane (q, g) of m-tile mt holds
@@ -412,123 +458,161 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q16 = lane & 15, grp = lane >> 4;
     const uint32_t stride = gridDim.x * kKeyWaves;
+    // Gated (compact layout, in-chunk levels only): the wave collects the
+    // pairs that pass model_gate from its tiles into full 64-row tiles of
+    // sX (with their pair indices in sIdx) and runs the model on those; the
+    // others get the cheapest level at once.  Otherwise every tile goes
+    // through the model, pair p in row p % 64.
+    const bool gated = CK && K.gate != 0u;
+    uint32_t n_buf = 0;
     uint32_t tile = blockIdx.x * kKeyWaves + wave;
     FeatWords cur = feat_words(P, (uint64_t)tile * 64 + lane);
-    for (; tile < P.n_tiles; tile += stride) {
+    for (;;) {
+        const bool have = tile < P.n_tiles;
         const uint64_t p = (uint64_t)tile * 64 + lane;
-        const bool all_long = !wave_any(cur.valid && cur.m < 64u + EF);
-        const bool masked = wave_any(cur.valid && cur.E < (uint32_t)EF);
-        if (CK && all_long && !masked) {
-            if (cur.valid) {
-                stage_compact_fast<EF>(cur.r0, cur.r1, cur.r2, cur.f0, cur.f1, cur.m, cur.E, &sX[wave][lane][0]);
+        uint32_t m = 0, E = 0;
+        bool valid = false;
+        if (have) {
+            const bool all_long = !wave_any(cur.valid && cur.m < 64u + EF);
+            const bool masked = wave_any(cur.valid && cur.E < (uint32_t)EF);
+            uint4 row[NF / 8];
+            bool pass = false;
+            if (CK && all_long && !masked) {
+                stage_compact_fast<EF>(cur.r0, cur.r1, cur.r2, cur.f0, cur.f1, cur.m, cur.E,
+                                       reinterpret_cast<uint4(&)[4]>(row), pass);
             } else {
+                float f[NF];
+                if (cur.valid) {
+                    features_from_words<EF, CK>(cur, f, all_long, masked, gated ? &pass : nullptr);
+                } else {
 #pragma unroll
-                for (int c = 0; c < NF / 8; ++c) *reinterpret_cast<uint4*>(&sX[wave][lane][8 * c]) = uint4{0, 0, 0, 0};
-            }
-        } else {
-            float f[NF];
-            if (cur.valid) {
-                features_from_words<EF, CK>(cur, f, all_long, masked);
-            } else {
-#pragma unroll
-                for (int i = 0; i < NF; ++i) f[i] = 0.0f;
-            }
-#pragma unroll
-            for (int c = 0; c < NF / 8; ++c) {
-                uint4 v;
-                v.x = bf16_bits(f[8 * c + 0]) | ((uint32_t)bf16_bits(f[8 * c + 1]) << 16);
-                v.y = bf16_bits(f[8 * c + 2]) | ((uint32_t)bf16_bits(f[8 * c + 3]) << 16);
-                v.z = bf16_bits(f[8 * c + 4]) | ((uint32_t)bf16_bits(f[8 * c + 5]) << 16);
-                v.w = bf16_bits(f[8 * c + 6]) | ((uint32_t)bf16_bits(f[8 * c + 7]) << 16);
-                *reinterpret_cast<uint4*>(&sX[wave][lane][8 * c]) = v;
-            }
-        }
-        const uint32_t m = cur.m, E = cur.E;
-        const bool valid = cur.valid;
-        // Next tile's words are fetched while this tile goes through the model.
-        if (tile + stride < P.n_tiles) cur = feat_words(P, (uint64_t)(tile + stride) * 64 + lane);
-        wave_lds_sync();
-        // Layer-1 operand B: X^T, lane (pair 16 nt + q16, group grp) holds
-        // features 32 kt + 8 grp .. +7 of its pair.
-        bf16x8 xf[KT1][4];
-#pragma unroll
-        for (int kt = 0; kt < KT1; ++kt)
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
-                xf[kt][nt] = *reinterpret_cast<const bf16x8*>(&sX[wave][16 * nt + q16][32 * kt + 8 * grp]);
-        f32x4 acc2[8][4];
-        // Layer 1 for the two m-tiles 2 kt2, 2 kt2 + 1 gives layer 2's operand
-        // B for k-tile kt2: relu(W1 x + b1) rounded to bf16 (ReLU applied to
-        // the packed bf16 pair as a 16-bit integer max: rounding keeps signs).
-        auto layer1 = [&](int kt2, bf16x8* b2) {
-#pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                const int mt1 = 2 * kt2 + half;
-                const f32x4 bias1 = *reinterpret_cast<const f32x4*>(&sB1[16 * mt1 + 4 * grp]);
-                f32x4 acc1[4];
-                const bf16x8 a1a = *reinterpret_cast<const bf16x8*>(&sW1[((mt1 * KT1 + 0) * 64 + lane) * 8]);
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt) acc1[nt] = mfma(a1a, xf[0][nt], bias1);
-                if constexpr (KT1 == 2) {
-                    const bf16x8 a1b = *reinterpret_cast<const bf16x8*>(&sW1[((mt1 * KT1 + 1) * 64 + lane) * 8]);
-#pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) acc1[nt] = mfma(a1b, xf[KT1 - 1][nt], acc1[nt]);
+                    for (int i = 0; i < NF; ++i) f[i] = 0.0f;
                 }
+                pack_row<NF>(f, row);
+            }
+            m = cur.m;
+            E = cur.E;
+            valid = cur.valid;
+            int r = lane;
+            if (gated) {
+                pass = pass && valid;
+                const uint64_t bal = __ballot(pass);
+                r = (int)n_buf + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                if (pass) sIdx[wave][r] = p;
+                else if (p < P.n_pairs && K.bucket) K.bucket[p] = 15u;   // level 0
+                n_buf += (uint32_t)__builtin_popcountll(bal);
+            }
+            if (!gated || pass) {
+#pragma unroll
+                for (int c = 0; c < NF / 8; ++c) *reinterpret_cast<uint4*>(&sX[wave][r][8 * c]) = row[c];
+            }
+            // Next tile's words are fetched while this one goes through the model.
+            if (tile + stride < P.n_tiles) cur = feat_words(P, (uint64_t)(tile + stride) * 64 + lane);
+        }
+        const uint32_t rows = gated ? (n_buf >= 64u ? 64u : (have ? 0u : n_buf)) : (have ? 64u : 0u);
+        if (rows > 0) {
+            wave_lds_sync();
+            // Layer-1 operand B: X^T, lane (row 16 nt + q16, group grp) holds
+            // features 32 kt + 8 grp .. +7 of its row.
+            bf16x8 xf[KT1][4];
+#pragma unroll
+            for (int kt = 0; kt < KT1; ++kt)
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
+                    xf[kt][nt] = *reinterpret_cast<const bf16x8*>(&sX[wave][16 * nt + q16][32 * kt + 8 * grp]);
+            f32x4 acc2[8][4];
+            // Layer 1 for the two m-tiles 2 kt2, 2 kt2 + 1 gives layer 2's operand
+            // B for k-tile kt2: relu(W1 x + b1) rounded to bf16 (ReLU applied to
+            // the packed bf16 pair as a 16-bit integer max: rounding keeps signs).
+            auto layer1 = [&](int kt2, bf16x8* b2) {
 #pragma unroll
-                    for (int i = 0; i < 4; i += 2) {
-                        const s16x2 v = relu_pk(acc1[nt][i], acc1[nt][i + 1]);
-                        b2[nt][4 * half + i] = __builtin_bit_cast(__bf16, (short)v[0]);
-                        b2[nt][4 * half + i + 1] = __builtin_bit_cast(__bf16, (short)v[1]);
+                for (int half = 0; half < 2; ++half) {
+                    const int mt1 = 2 * kt2 + half;
+                    const f32x4 bias1 = *reinterpret_cast<const f32x4*>(&sB1[16 * mt1 + 4 * grp]);
+                    f32x4 acc1[4];
+                    const bf16x8 a1a = *reinterpret_cast<const bf16x8*>(&sW1[((mt1 * KT1 + 0) * 64 + lane) * 8]);
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) acc1[nt] = mfma(a1a, xf[0][nt], bias1);
+                    if constexpr (KT1 == 2) {
+                        const bf16x8 a1b =
+                            *reinterpret_cast<const bf16x8*>(&sW1[((mt1 * KT1 + 1) * 64 + lane) * 8]);
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt) acc1[nt] = mfma(a1b, xf[KT1 - 1][nt], acc1[nt]);
                     }
-            }
-        };
-        {
-            // k-tile 0: the accumulators start from the bias (C operand).
-            bf16x8 b2[4];
-            layer1(0, b2);
 #pragma unroll
-            for (int mt2 = 0; mt2 < 8; ++mt2) {
-                const f32x4 bias2 = *reinterpret_cast<const f32x4*>(&sB2[16 * mt2 + 4 * grp]);
-                const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(&sW2[((mt2 * 4 + 0) * 64 + lane) * 8]);
+                    for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt) acc2[mt2][nt] = mfma(a2, b2[nt], bias2);
+                        for (int i = 0; i < 4; i += 2) {
+                            const s16x2 v = relu_pk(acc1[nt][i], acc1[nt][i + 1]);
+                            b2[nt][4 * half + i] = __builtin_bit_cast(__bf16, (short)v[0]);
+                            b2[nt][4 * half + i + 1] = __builtin_bit_cast(__bf16, (short)v[1]);
+                        }
+                }
+            };
+            {
+                // k-tile 0: the accumulators start from the bias (C operand).
+                bf16x8 b2[4];
+                layer1(0, b2);
+#pragma unroll
+                for (int mt2 = 0; mt2 < 8; ++mt2) {
+                    const f32x4 bias2 = *reinterpret_cast<const f32x4*>(&sB2[16 * mt2 + 4 * grp]);
+                    const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(&sW2[((mt2 * 4 + 0) * 64 + lane) * 8]);
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) acc2[mt2][nt] = mfma(a2, b2[nt], bias2);
+                }
             }
-        }
 #pragma unroll 1
-        for (int kt2 = 1; kt2 < 4; ++kt2) {
-            bf16x8 b2[4];
-            layer1(kt2, b2);
+            for (int kt2 = 1; kt2 < 4; ++kt2) {
+                bf16x8 b2[4];
+                layer1(kt2, b2);
 #pragma unroll
-            for (int mt2 = 0; mt2 < 8; ++mt2) {
-                const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(&sW2[((mt2 * 4 + kt2) * 64 + lane) * 8]);
+                for (int mt2 = 0; mt2 < 8; ++mt2) {
+                    const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(&sW2[((mt2 * 4 + kt2) * 64 + lane) * 8]);
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt) acc2[mt2][nt] = mfma(a2, b2[nt], acc2[mt2][nt]);
+                    for (int nt = 0; nt < 4; ++nt) acc2[mt2][nt] = mfma(a2, b2[nt], acc2[mt2][nt]);
+                }
+            }
+            // Head: y = w3 . relu(layer 2) + b3; lane l ends with row l.
+            float yv = 0.0f;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                float t = 0.0f;
+#pragma unroll
+                for (int mt2 = 0; mt2 < 8; ++mt2)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) t += sW3[16 * mt2 + 4 * grp + i] * relu_bits(acc2[mt2][nt][i]);
+                t += __shfl_xor(t, 16);
+                t += __shfl_xor(t, 32);
+                if (grp == nt) yv = t;
+            }
+            const float y = yv + b3;
+            if (gated) {
+                if ((uint32_t)lane < rows && K.bucket) K.bucket[sIdx[wave][lane]] = (uint8_t)(15u - chunk_level(y));
+            } else if (p < P.n_pairs) {
+                if (K.pred) K.pred[p] = valid ? y : 0.0f;
+                if (K.bucket) {
+                    const uint32_t lv = K.chunk_key ? chunk_level(y) : cost_bucket(y, m, E, P.max_len, P.max_E);
+                    K.bucket[p] = (uint8_t)(valid ? 15u - lv : 15u);
+                }
+            }
+            wave_lds_sync();
+            if (gated) {
+                // Rows past the first 64 move to the front for the next tile.
+                const uint32_t rest = n_buf - rows;
+                if (rows == 64u && (uint32_t)lane < rest) {
+#pragma unroll
+                    for (int c = 0; c < NF / 8; ++c)
+                        *reinterpret_cast<uint4*>(&sX[wave][lane][8 * c]) =
+                            *reinterpret_cast<const uint4*>(&sX[wave][64 + lane][8 * c]);
+                    sIdx[wave][lane] = sIdx[wave][64 + lane];
+                }
+                n_buf = rest;
+                wave_lds_sync();
             }
         }
-        // Head: y = w3 . relu(layer 2) + b3; lane l ends with pair l.
-        float yv = 0.0f;
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            float t = 0.0f;
-#pragma unroll
-            for (int mt2 = 0; mt2 < 8; ++mt2)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) t += sW3[16 * mt2 + 4 * grp + i] * relu_bits(acc2[mt2][nt][i]);
-            t += __shfl_xor(t, 16);
-            t += __shfl_xor(t, 32);
-            if (grp == nt) yv = t;
-        }
-        const float y = yv + b3;
-        if (p < P.n_pairs) {
-            if (K.pred) K.pred[p] = valid ? y : 0.0f;
-            if (K.bucket) {
-                const uint32_t lv = K.chunk_key ? chunk_level(y) : cost_bucket(y, m, E, P.max_len, P.max_E);
-                K.bucket[p] = (uint8_t)(valid ? 15u - lv : 15u);
-            }
-        }
-        wave_lds_sync();
+        if (!have) break;
+        tile += stride;
     }
 }
 
@@ -912,6 +996,7 @@ hipError_t launch_learned_buckets(const MlpDev& m, const FilterParams& p, int nu
     kp.pred = pred;
     kp.bucket = bucket;
     kp.chunk_key = chunk_key ? 1u : 0u;
+    kp.gate = chunk_key && !pred ? 1u : 0u;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64 * kKeyWaves, 0) != hipSuccess || nb < 1) nb = 1;
     const uint32_t want = (uint32_t)(num_cus * nb);

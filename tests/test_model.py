@@ -358,16 +358,43 @@ def test_chunk_level_properties():
     assert all(a <= b for a, b in zip(lv, lv[1:]))
 
 
+def model_gate_host(p) -> np.ndarray:
+    """Which pairs the level call runs the model on (compact feature layout,
+    max_E up to 12): some diagonal |d| <= E whose matching cells make up at
+    least 2/5 of the first min(m, 64) columns, from the oracle's features
+    (exact fractions matches / columns)."""
+    F = oracle.features_batch(p.reads, p.refs, p.len, p.E)
+    cols = np.minimum(p.len, 64).astype(np.int64)
+    matches = np.rint(F[:, 32 - 30:32 + 31] * cols[:, None]).astype(np.int64)
+    d = np.arange(-30, 31)
+    inside = np.abs(d)[None, :] <= p.E[:, None]
+    return ((5 * matches >= 2 * cols[:, None]) & inside).any(axis=1)
+
+
 @gpu
 def test_cost_levels_match_predictions(gpu_ctx):
-    """The fused model's level key is 15 - level of its own prediction."""
+    """The fused model's level key is 15 - level of its own prediction; with
+    the compact feature layout (max_E up to 12) only the pairs that pass the
+    gate run the model, the others get level 0 (key 15)."""
+    from gpu_util import to_device
     _set_random_model(gpu_ctx, seed=13)
-    for w, n in ((pairgen.UNEVEN_MIX, 30_000), (pairgen.FIXED_250BP, 9_001)):
-        b = _workload_batch(gpu_ctx, w, n)
+    short = pairgen.generate(pairgen.UNEVEN_MIX, 0, 20_000)
+    short.E = np.minimum(short.E, 12).astype(short.E.dtype)   # lengths from 64: the counting path with masks
+    cases = [("uneven, max_E 15", _workload_batch(gpu_ctx, pairgen.UNEVEN_MIX, 30_000), None),
+             ("250 bp, E 10", _workload_batch(gpu_ctx, pairgen.FIXED_250BP, 9_001),
+              pairgen.generate(pairgen.FIXED_250BP, 0, 9_001)),
+             ("100 bp, E 5", _workload_batch(gpu_ctx, pairgen.SMALL_100BP, 7_777),
+              pairgen.generate(pairgen.SMALL_100BP, 0, 7_777)),
+             ("uneven, max_E 12", to_device(short, gpu_ctx, per_pair=True, offsets=True), short)]
+    for name, b, p in cases:
         y = gpu_ctx.mlp_predict(b).cpu().numpy()
         key = gpu_ctx.cost_levels(b).cpu().numpy().astype(np.int64)
         want = np.array([15 - chunk_level_host(v) for v in y])
-        assert np.array_equal(key, want)
+        if p is not None:
+            gate = model_gate_host(p)
+            assert 0.05 < gate.mean() < 0.95, (name, gate.mean())
+            want = np.where(gate, want, 15)
+        assert np.array_equal(key, want), name
 
 
 @gpu
