@@ -290,14 +290,27 @@ def test_bucketed_filter_equals_plain(gpu_ctx, filters):
 def test_bucketed_local_equals_plain(gpu_ctx):
     """Chunk-local bucketing (model levels order each compacting chunk):
     identical decisions to the plain filter and the oracle, on uniform and
-    per-pair layouts, ragged batches, graph replays and several layouts."""
+    per-pair layouts, ragged batches, graph replays and several layouts:
+    uniform 250 bp at E 0, 5, 10 and 12 and the uneven mix with E capped at
+    12 (the gated model: only some pairs get a level from the network), and
+    the uneven mix at max_E 15 (every pair runs the model)."""
     import paper_1910_03936_amd as paf
+    from gpu_util import to_device
     SS = paf.SNEAKYSNAKE
+    capped = pairgen.generate(pairgen.UNEVEN_MIX, 0, 20_001)
+    capped.E = np.minimum(capped.E, 12).astype(capped.E.dtype)
     for seed in (10, 11):
         _set_random_model(gpu_ctx, seed=seed)
-        for w, n in ((pairgen.UNEVEN_MIX, 20_001), (pairgen.FIXED_250BP, 9_000), (pairgen.FIXED_250BP, 65)):
-            b = _workload_batch(gpu_ctx, w, n)
-            p = pairgen.generate(w, 0, n)
+        cases = [(pairgen.UNEVEN_MIX, 20_001), (pairgen.FIXED_250BP, 9_000), (pairgen.FIXED_250BP, 65),
+                 (pairgen.FIXED_250BP.with_E(0), 4_001), (pairgen.FIXED_250BP.with_E(5), 4_001),
+                 (pairgen.FIXED_250BP.with_E(12), 4_001), ("uneven, E capped at 12", None)]
+        for w, n in cases:
+            if n is None:
+                p, n = capped, capped.n
+                b = to_device(p, gpu_ctx, per_pair=True, offsets=True)
+            else:
+                b = _workload_batch(gpu_ctx, w, n)
+                p = pairgen.generate(w, 0, n)
             want = oracle.filter_batch(p.reads, p.refs, p.len, p.E, SS)[SS]
             for lay in (None, {"lanes_per_pair": 1, "waves_per_block": 4, "blocks_per_cu": 2,
                                "tiles_per_grab": 1, "chunk_tiles": 3},
@@ -308,26 +321,30 @@ def test_bucketed_local_equals_plain(gpu_ctx):
                     for rep in range(2):   # capture, then replay
                         got = gpu_ctx.filter_bucketed_local(b)
                         acc = paf.accept_bits_to_bool(got[SS][0], n).cpu().numpy().astype(np.uint8)
-                        assert np.array_equal(acc, want[0]), (w.name, n, lay, rep)
+                        name = w if isinstance(w, str) else w.name
+                        assert np.array_equal(acc, want[0]), (name, n, lay, rep)
                         assert np.array_equal(paf.counts_u16(got[SS][1]).cpu().numpy(),
-                                              want[1].astype(np.int64)), (w.name, n, lay, rep)
+                                              want[1].astype(np.int64)), (name, n, lay, rep)
                 finally:
                     gpu_ctx.set_layout(None)
     gpu_ctx.check()
 
 
 @gpu
-def test_bucketed_local_range_violation(gpu_ctx):
+@pytest.mark.parametrize("cap", [15, 12])
+def test_bucketed_local_range_violation(gpu_ctx, cap):
+    """A pair above the batch's max_E sets the range flag and gets zero
+    outputs; the others keep theirs (max_E 12: the gated model)."""
     import paper_1910_03936_amd as paf
     SS = paf.SNEAKYSNAKE
     _set_random_model(gpu_ctx, seed=12)
     p = pairgen.generate(pairgen.UNEVEN_MIX, 0, 1000)
-    E = p.E.copy()
+    E = np.minimum(p.E, cap).astype(p.E.dtype)
     E[333] = 20
     dev = torch.device("cuda", 0)
     b = gpu_ctx.pack_pairs(torch.from_numpy(p.reads).to(dev), torch.from_numpy(p.refs).to(dev),
                            lens=torch.from_numpy(p.len.astype(np.int16)).to(dev),
-                           Es=torch.from_numpy(E).to(dev), max_len=int(p.len.max()), max_E=15, offsets=True)
+                           Es=torch.from_numpy(E).to(dev), max_len=int(p.len.max()), max_E=cap, offsets=True)
     got = gpu_ctx.filter_bucketed_local(b)
     torch.cuda.synchronize()
     with pytest.raises(paf.PafError):
@@ -335,7 +352,7 @@ def test_bucketed_local_range_violation(gpu_ctx):
     acc = paf.accept_bits_to_bool(got[SS][0], p.n).cpu().numpy()
     cnt = paf.counts_u16(got[SS][1]).cpu().numpy()
     assert acc[333] == 0 and cnt[333] == 0
-    want = oracle.filter_batch(p.reads, p.refs, p.len, p.E, SS)[SS]
+    want = oracle.filter_batch(p.reads, p.refs, p.len, E, SS)[SS]
     mask = np.arange(p.n) != 333
     assert np.array_equal(cnt[mask], want[1][mask].astype(np.int64))
     assert np.array_equal(acc[mask].astype(np.uint8), want[0][mask])
