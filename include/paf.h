@@ -382,11 +382,11 @@ paf_status paf_filter_bucketed(paf_ctx* ctx, const paf_batch* batch, uint32_t fi
  * y the predicted SneakySnake count at E = 31 (key: uint8 [device],
  * n_pairs entries, original order).  The compacting filter reads a pair's
  * key only if the pair is still undecided after the first pass (its first
- * 64 columns), so up to max_E 12 (the compact feature layout) the model runs
- * only on the pairs with a diagonal |d| <= E whose matching cells make up at
- * least 2/5 of the first min(m, 64) columns (5 matches >= 2 columns); the
- * others, which that pass almost always decides, get level 0 (key 15)
- * without it.  Above max_E 12 every pair runs the model. */
+ * 64 columns), so up to max_E 15 (the compact feature layouts) the model
+ * runs only on the pairs with a diagonal |d| <= E whose matching cells make
+ * up at least 2/5 of the first min(m, 64) columns (5 matches >= 2 columns);
+ * the others, which that pass almost always decides, get level 0 (key 15)
+ * without it.  Above max_E 15 every pair runs the model. */
 paf_status paf_cost_levels(paf_ctx* ctx, const paf_batch* batch, uint8_t* key, void* stream);
 
 /* Stage 2: SneakySnake alone on the compacting engine, the pairs of each

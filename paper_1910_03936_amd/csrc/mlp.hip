@@ -153,12 +153,14 @@ __device__ __forceinline__ bool model_gate(uint32_t matches, uint32_t cols) {
     return 5u * matches >= 2u * cols;
 }
 
-template <int EF, bool CK = false>
+// NF = 64: the model's own input layout; NF < 64: the compact one (only the
+// non-zero inputs, in slots 0 .. 2 EF + 2).
+template <int EF, int NF = 64>
 __device__ __forceinline__ void pair_features(const uint64_t* rd, const uint64_t* rf, uint32_t m,
                                               uint32_t E, float* f, bool all_long, bool masked,
                                               bool* gate = nullptr) {
     constexpr int D = 2 * EF + 1;
-    constexpr int NF = CK ? 32 : 64;
+    constexpr bool CK = NF < 64;
     uint32_t z[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) z[i] = 0;
@@ -256,9 +258,9 @@ __device__ __forceinline__ void blocked_counts(uint32_t plo, uint32_t phi, uint3
     }
 }
 
-template <int EF>
+template <int EF, int NF>
 __device__ __forceinline__ void stage_compact_fast(uint64_t r0, uint64_t r1, uint64_t r2, uint64_t f0,
-                                                   uint64_t f1, uint32_t m, uint32_t E, uint4 (&row)[4],
+                                                   uint64_t f1, uint32_t m, uint32_t E, uint4 (&row)[NF / 8],
                                                    bool& gate) {
     constexpr int D = 2 * EF + 1;
     uint32_t z[D];
@@ -268,14 +270,14 @@ __device__ __forceinline__ void stage_compact_fast(uint64_t r0, uint64_t r1, uin
                    r1h = (uint32_t)(r1 >> 32), r2l = (uint32_t)r2, r2h = (uint32_t)(r2 >> 32);
     blocked_counts<EF, 0>(0u, 0u, r0l, r0h, r1l, r1h, (uint32_t)f0, (uint32_t)(f0 >> 32), z);
     blocked_counts<EF, 1>(r0l, r0h, r1l, r1h, r2l, r2h, (uint32_t)f1, (uint32_t)(f1 >> 32), z);
-    float v[32];
+    float v[NF];
     v[0] = (float)m * (1.0f / 512.0f);
     v[1] = (float)E * (1.0f / 32.0f);
 #pragma unroll
     for (int i = 0; i < D; ++i) v[2 + i] = __builtin_fmaf((float)z[i], -1.0f / 64.0f, 1.0f);
 #pragma unroll
-    for (int i = D + 2; i < 32; ++i) v[i] = 0.0f;
-    pack_row<32>(v, row);
+    for (int i = D + 2; i < NF; ++i) v[i] = 0.0f;
+    pack_row<NF>(v, row);
     // Every lane of the wave has E >= EF here: all diagonals are inside it.
     bool g = false;
 #pragma unroll
@@ -405,23 +407,27 @@ __device__ __forceinline__ FeatWords feat_words(const FilterParams& P, uint64_t 
     return q;
 }
 
-template <int EF, bool CK>
+template <int EF, int NF>
 __device__ __forceinline__ void features_from_words(const FeatWords& w, float* f, bool all_long,
                                                     bool masked, bool* gate) {
     uint64_t rd[3] = {w.r0, w.r1, w.r2};
     uint64_t rf[2] = {w.f0, w.f1};
-    pair_features<EF, CK>(rd, rf, w.m, w.E, f, all_long, masked, gate);
+    pair_features<EF, NF>(rd, rf, w.m, w.E, f, all_long, masked, gate);
 }
 
 // With at most 14 diagonals per side the non-zero inputs (m/512, E/32 and
 // the 2 EF + 1 fractions) fit one 32-wide k-tile: the kernel stages that
 // compact vector and layer 1 takes one matrix product per tile instead of
-// two (the other 32 inputs are zero and add nothing).
+// two (the other 32 inputs are zero and add nothing).  Up to 18 per side
+// they fit 40 slots: still two k-tiles, but the staged rows (and so the
+// rows a gated wave can hold) stay small.
 template <int EF>
 __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
-    constexpr bool CK = 2 * EF + 3 <= 32;
-    constexpr int KT1 = CK ? 1 : 2;          // layer-1 k-tiles
-    constexpr int NF = 32 * KT1;             // staged inputs per pair
+    // Staged inputs per pair: the 2 EF + 3 non-zero ones in 32 or 40 slots
+    // (compact), else the model's 64.
+    constexpr int NF = 2 * EF + 3 <= 32 ? 32 : (2 * EF + 3 <= 40 ? 40 : 64);
+    constexpr bool CK = NF < 64;
+    constexpr int KT1 = NF > 32 ? 2 : 1;     // layer-1 k-tiles
     __shared__ __attribute__((aligned(16))) uint16_t sW1[8 * KT1 * 64 * 8];
     __shared__ __attribute__((aligned(16))) uint16_t sW2[8 * 4 * 64 * 8];
     __shared__ __attribute__((aligned(16))) float sB1[kHid];
@@ -434,11 +440,11 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
     __shared__ uint64_t sIdx[kKeyWaves][CK ? 128 : 1];
     const FilterParams& P = K.P;
     if constexpr (CK) {
-        // Fragment order for one k-tile: lane (q, g) of m-tile mt holds
-        // W1[16 mt + q][input of compact slot 8 g + j], j = 0..7.
-        for (int i = threadIdx.x; i < 8 * 64 * 8; i += blockDim.x) {
-            const int j = i & 7, ln = (i >> 3) & 63, mt = i >> 9;
-            const int h = 16 * mt + (ln & 15), slot = 8 * (ln >> 4) + j;
+        // Fragment order: lane (q, g) of m-tile mt, k-tile kt holds
+        // W1[16 mt + q][input of compact slot 32 kt + 8 g + j], j = 0..7.
+        for (int i = threadIdx.x; i < 8 * KT1 * 64 * 8; i += blockDim.x) {
+            const int j = i & 7, ln = (i >> 3) & 63, kt = (i >> 9) % KT1, mt = (i >> 9) / KT1;
+            const int h = 16 * mt + (ln & 15), slot = 32 * kt + 8 * (ln >> 4) + j;
             const int in = slot < 2 ? slot : (slot - 2 <= 2 * EF ? 32 - EF + (slot - 2) : -1);
             sW1[i] = in < 0 ? (uint16_t)0 : K.w1b[h * kFeat + in];
         }
@@ -478,12 +484,11 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
             uint4 row[NF / 8];
             bool pass = false;
             if (CK && all_long && !masked) {
-                stage_compact_fast<EF>(cur.r0, cur.r1, cur.r2, cur.f0, cur.f1, cur.m, cur.E,
-                                       reinterpret_cast<uint4(&)[4]>(row), pass);
+                stage_compact_fast<EF, NF>(cur.r0, cur.r1, cur.r2, cur.f0, cur.f1, cur.m, cur.E, row, pass);
             } else {
                 float f[NF];
                 if (cur.valid) {
-                    features_from_words<EF, CK>(cur, f, all_long, masked, gated ? &pass : nullptr);
+                    features_from_words<EF, NF>(cur, f, all_long, masked, gated ? &pass : nullptr);
                 } else {
 #pragma unroll
                     for (int i = 0; i < NF; ++i) f[i] = 0.0f;
@@ -520,7 +525,9 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
             for (int kt = 0; kt < KT1; ++kt)
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
-                    xf[kt][nt] = *reinterpret_cast<const bf16x8*>(&sX[wave][16 * nt + q16][32 * kt + 8 * grp]);
+                    xf[kt][nt] = 32 * kt + 8 * grp < NF
+                                     ? *reinterpret_cast<const bf16x8*>(&sX[wave][16 * nt + q16][32 * kt + 8 * grp])
+                                     : bf16x8{};
             f32x4 acc2[8][4];
             // Layer 1 for the two m-tiles 2 kt2, 2 kt2 + 1 gives layer 2's operand
             // B for k-tile kt2: relu(W1 x + b1) rounded to bf16 (ReLU applied to

@@ -291,9 +291,9 @@ def test_bucketed_local_equals_plain(gpu_ctx):
     """Chunk-local bucketing (model levels order each compacting chunk):
     identical decisions to the plain filter and the oracle, on uniform and
     per-pair layouts, ragged batches, graph replays and several layouts:
-    uniform 250 bp at E 0, 5, 10 and 12 and the uneven mix with E capped at
-    12 (the gated model: only some pairs get a level from the network), and
-    the uneven mix at max_E 15 (every pair runs the model)."""
+    uniform 250 bp at E 0, 5, 10 and 12, the uneven mix at max_E 15 and with E
+    capped at 12 (the gated model: only some pairs get a level from the
+    network)."""
     import paper_1910_03936_amd as paf
     from gpu_util import to_device
     SS = paf.SNEAKYSNAKE
@@ -334,7 +334,7 @@ def test_bucketed_local_equals_plain(gpu_ctx):
 @pytest.mark.parametrize("cap", [15, 12])
 def test_bucketed_local_range_violation(gpu_ctx, cap):
     """A pair above the batch's max_E sets the range flag and gets zero
-    outputs; the others keep theirs (max_E 12: the gated model)."""
+    outputs; the others keep theirs (both with the gated model)."""
     import paper_1910_03936_amd as paf
     SS = paf.SNEAKYSNAKE
     _set_random_model(gpu_ctx, seed=12)
@@ -376,8 +376,8 @@ def test_chunk_level_properties():
 
 
 def model_gate_host(p) -> np.ndarray:
-    """Which pairs the level call runs the model on (compact feature layout,
-    max_E up to 12): some diagonal |d| <= E whose matching cells make up at
+    """Which pairs the level call runs the model on (compact feature layouts,
+    max_E up to 15): some diagonal |d| <= E whose matching cells make up at
     least 2/5 of the first min(m, 64) columns, from the oracle's features
     (exact fractions matches / columns)."""
     F = oracle.features_batch(p.reads, p.refs, p.len, p.E)
@@ -391,13 +391,15 @@ def model_gate_host(p) -> np.ndarray:
 @gpu
 def test_cost_levels_match_predictions(gpu_ctx):
     """The fused model's level key is 15 - level of its own prediction; with
-    the compact feature layout (max_E up to 12) only the pairs that pass the
+    the compact feature layouts (max_E up to 15) only the pairs that pass the
     gate run the model, the others get level 0 (key 15)."""
     from gpu_util import to_device
     _set_random_model(gpu_ctx, seed=13)
     short = pairgen.generate(pairgen.UNEVEN_MIX, 0, 20_000)
     short.E = np.minimum(short.E, 12).astype(short.E.dtype)   # lengths from 64: the counting path with masks
-    cases = [("uneven, max_E 15", _workload_batch(gpu_ctx, pairgen.UNEVEN_MIX, 30_000), None),
+    cases = [("uneven, max_E 15", _workload_batch(gpu_ctx, pairgen.UNEVEN_MIX, 30_000),
+              pairgen.generate(pairgen.UNEVEN_MIX, 0, 30_000)),
+             ("250 bp, E 25", _workload_batch(gpu_ctx, pairgen.FIXED_250BP.with_E(25), 5_001), None),
              ("250 bp, E 10", _workload_batch(gpu_ctx, pairgen.FIXED_250BP, 9_001),
               pairgen.generate(pairgen.FIXED_250BP, 0, 9_001)),
              ("100 bp, E 5", _workload_batch(gpu_ctx, pairgen.SMALL_100BP, 7_777),
