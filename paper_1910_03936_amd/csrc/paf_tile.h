@@ -59,12 +59,19 @@ __device__ __forceinline__ PairSlot load_slot(const FilterParams& P, uint64_t ti
     return s;
 }
 
+constexpr int kStageBatch = 8;
+
 // Stage the tile's words into the wave's LDS rows.
 template <bool GENERAL>
 __device__ __forceinline__ void stage_tile(const FilterParams& P, uint64_t tile, int lane,
                                            const PairSlot& s, uint64_t off, uint64_t* rdL,
                                            uint64_t* rfL) {
     const uint32_t WM = P.wmax;
+    // Loads go out kStageBatch at a time before their LDS stores, so a
+    // wave waits for memory once per batch instead of once per load; a load
+    // with nothing to fetch reads word 0 of the array (always there) and is
+    // discarded, so no load sits behind a branch.
+    constexpr int B = kStageBatch;
     if (!GENERAL) {
         // The tile's pairs are contiguous: pair-major rows of stride_words
         // words.  Coalesced 8-byte loads over the whole tile region, then a
@@ -76,16 +83,31 @@ __device__ __forceinline__ void stage_tile(const FilterParams& P, uint64_t tile,
         uint32_t q = (uint32_t)lane;
         uint32_t pr = q / S, k = q - pr * S;
         const uint32_t dp = 64u / S, dk = 64u - dp * S;
-        for (; q < total; q += 64) {
-            if (k < WM) {
+        while (q < total) {
+            uint64_t vr[B], vf[B];
+            uint32_t at[B];
+            bool use[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
                 const uint64_t g = base + q;
-                const bool ok = g < limit;
-                rdL[k * kLdsRow + pr] = ok ? P.reads[g] : 0ull;
-                rfL[k * kLdsRow + pr] = ok ? P.refs[g] : 0ull;
+                use[b] = q < total && k < WM;
+                const bool ok = use[b] && g < limit;
+                const uint64_t a = ok ? g : 0ull;
+                const uint64_t xr = P.reads[a], xf = P.refs[a];
+                vr[b] = ok ? xr : 0ull;
+                vf[b] = ok ? xf : 0ull;
+                at[b] = k * kLdsRow + pr;
+                q += 64;
+                pr += dp;
+                k += dk;
+                if (k >= S) { k -= S; pr += 1; }
             }
-            pr += dp;
-            k += dk;
-            if (k >= S) { k -= S; pr += 1; }
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+                if (use[b]) {
+                    rdL[at[b]] = vr[b];
+                    rfL[at[b]] = vf[b];
+                }
         }
         // Words past a pair's length are zero already (the packer zeroes the
         // tail of the last word and the layout has no words beyond W).
@@ -98,14 +120,31 @@ __device__ __forceinline__ void stage_tile(const FilterParams& P, uint64_t tile,
         const uint32_t wv = s.valid ? s.W : 0u;
         uint32_t pr = (uint32_t)lane / WM, k = (uint32_t)lane - pr * WM;
         const uint32_t dp = 64u / WM, dk = 64u - dp * WM;
-        for (uint32_t r = 0; r < WM; ++r) {
-            const uint64_t o = ((uint64_t)__shfl(offhi, (int)pr) << 32) | __shfl(offlo, (int)pr);
-            const bool ok = k < (uint32_t)__shfl(wv, (int)pr);
-            rdL[k * kLdsRow + pr] = ok ? P.reads[o + k] : 0ull;
-            rfL[k * kLdsRow + pr] = ok ? P.refs[o + k] : 0ull;
-            pr += dp;
-            k += dk;
-            if (k >= WM) { k -= WM; pr += 1; }
+        for (uint32_t r0 = 0; r0 < WM; r0 += B) {
+            uint64_t vr[B], vf[B];
+            uint32_t at[B];
+            bool use[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const uint64_t o = ((uint64_t)__shfl(offhi, (int)pr) << 32) | __shfl(offlo, (int)pr);
+                const uint32_t wp = (uint32_t)__shfl(wv, (int)pr);
+                use[b] = r0 + (uint32_t)b < WM;
+                const bool ok = use[b] && k < wp;
+                const uint64_t a = ok ? o + k : 0ull;
+                const uint64_t xr = P.reads[a], xf = P.refs[a];
+                vr[b] = ok ? xr : 0ull;
+                vf[b] = ok ? xf : 0ull;
+                at[b] = k * kLdsRow + pr;
+                pr += dp;
+                k += dk;
+                if (k >= WM) { k -= WM; pr += 1; }
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+                if (use[b]) {
+                    rdL[at[b]] = vr[b];
+                    rfL[at[b]] = vf[b];
+                }
         }
     }
     wave_lds_sync();

@@ -303,7 +303,7 @@ def test_bucketed_local_equals_plain(gpu_ctx):
         _set_random_model(gpu_ctx, seed=seed)
         cases = [(pairgen.UNEVEN_MIX, 20_001), (pairgen.FIXED_250BP, 9_000), (pairgen.FIXED_250BP, 65),
                  (pairgen.FIXED_250BP.with_E(0), 4_001), (pairgen.FIXED_250BP.with_E(5), 4_001),
-                 (pairgen.FIXED_250BP.with_E(12), 4_001), ("uneven, E capped at 12", None)]
+                 (pairgen.FIXED_250BP.with_E(12), 4_001), ("uneven, E capped at 12", None), (SHORT_MIX, 10_001)]
         for w, n in cases:
             if n is None:
                 p, n = capped, capped.n
@@ -375,6 +375,11 @@ def test_chunk_level_properties():
     assert all(a <= b for a, b in zip(lv, lv[1:]))
 
 
+# Pairs shorter than the feature window (64 columns) and shorter than 64 + E,
+# so the gate counts over min(m, 64) columns on the masked path: E = floor(m / 6).
+SHORT_MIX = pairgen.Workload("short", 20_000, (5, 17, 31, 47, 63, 70, 75), 12, 0.5, -1, 1, 6)
+
+
 def model_gate_host(p) -> np.ndarray:
     """Which pairs the level call runs the model on (compact feature layouts,
     max_E up to 15): some diagonal |d| <= E whose matching cells make up at
@@ -404,7 +409,8 @@ def test_cost_levels_match_predictions(gpu_ctx):
               pairgen.generate(pairgen.FIXED_250BP, 0, 9_001)),
              ("100 bp, E 5", _workload_batch(gpu_ctx, pairgen.SMALL_100BP, 7_777),
               pairgen.generate(pairgen.SMALL_100BP, 0, 7_777)),
-             ("uneven, max_E 12", to_device(short, gpu_ctx, per_pair=True, offsets=True), short)]
+             ("uneven, max_E 12", to_device(short, gpu_ctx, per_pair=True, offsets=True), short),
+             ("5-75 bp, E = m / 6", _workload_batch(gpu_ctx, SHORT_MIX, 20_000), pairgen.generate(SHORT_MIX, 0, 20_000))]
     for name, b, p in cases:
         y = gpu_ctx.mlp_predict(b).cpu().numpy()
         key = gpu_ctx.cost_levels(b).cpu().numpy().astype(np.int64)
