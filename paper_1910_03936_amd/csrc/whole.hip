@@ -29,37 +29,47 @@ struct ShoujiBest {
     uint32_t b0, b1, b2, b3;  // the best segment's bits
 };
 
+// Three-input logic in one v_bitop3 each (truth table bit s0 * 4 + s1 * 2 + s2):
+// m ? x : y; a ^ b ^ c; and one step of a bit-sliced less-than from the low
+// bit up, (~n & o) | (~(n ^ o) & t).
+__device__ __forceinline__ uint32_t sel3(uint32_t m, uint32_t x, uint32_t y) {
+    return __builtin_amdgcn_bitop3_b32(m, x, y, 0xCA);
+}
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+__device__ __forceinline__ uint32_t lt_step(uint32_t n, uint32_t o, uint32_t t) {
+    return __builtin_amdgcn_bitop3_b32(n, o, t, 0x8E);
+}
+
 __device__ __forceinline__ void shouji_candidate(ShoujiBest& bs, uint32_t cur, uint32_t nxt,
                                                  bool first) {
     const uint32_t B0 = cur;
     const uint32_t B1 = funnel(nxt, cur, 1);
     const uint32_t B2 = funnel(nxt, cur, 2);
     const uint32_t B3 = funnel(nxt, cur, 3);
+    // Ones in the segment, bit-sliced: n = B0 + B1 + B2 + B3 (0..4).
     const uint32_t s01 = B0 ^ B1, c01 = B0 & B1, s23 = B2 ^ B3, c23 = B2 & B3;
-    const uint32_t o0 = s01 ^ s23;
-    const uint32_t cm = s01 & s23;
-    const uint32_t o1 = c01 ^ c23 ^ cm;
-    const uint32_t o2 = c01 & c23;
+    const uint32_t n0 = s01 ^ s23;
+    const uint32_t n1 = xor3(c01, c23, s01 & s23);
+    const uint32_t n2 = c01 & c23;
     if (first) {
-        bs = {o0, o1, o2, B0, B1, B2, B3};
+        bs = {n0, n1, n2, B0, B1, B2, B3};
         return;
     }
     // Fewer ones wins; on a tie, a segment that starts with a zero beats one
-    // that does not; otherwise the earlier diagonal is kept.
-    const uint32_t t0 = ~o0 & bs.o0;
-    const uint32_t e1 = ~(o1 ^ bs.o1);
-    const uint32_t t1 = (~o1 & bs.o1) | (e1 & t0);
-    const uint32_t e2 = ~(o2 ^ bs.o2);
-    const uint32_t lt = (~o2 & bs.o2) | (e2 & t1);
-    const uint32_t eq = e2 & e1 & ~(o0 ^ bs.o0);
-    const uint32_t rep = lt | (eq & ~B0 & bs.b0);
-    bs.o0 = (rep & o0) | (~rep & bs.o0);
-    bs.o1 = (rep & o1) | (~rep & bs.o1);
-    bs.o2 = (rep & o2) | (~rep & bs.o2);
-    bs.b0 = (rep & B0) | (~rep & bs.b0);
-    bs.b1 = (rep & B1) | (~rep & bs.b1);
-    bs.b2 = (rep & B2) | (~rep & bs.b2);
-    bs.b3 = (rep & B3) | (~rep & bs.b3);
+    // that does not; otherwise the earlier diagonal is kept.  That is one
+    // strict comparison of the keys 2 n + B0 and 2 o + b0, bit-sliced from
+    // the lowest bit up: t = new < best on the bits seen so far.
+    const uint32_t t0 = ~B0 & bs.b0;
+    const uint32_t rep = lt_step(n2, bs.o2, lt_step(n1, bs.o1, lt_step(n0, bs.o0, t0)));
+    bs.o0 = sel3(rep, n0, bs.o0);
+    bs.o1 = sel3(rep, n1, bs.o1);
+    bs.o2 = sel3(rep, n2, bs.o2);
+    bs.b0 = sel3(rep, B0, bs.b0);
+    bs.b1 = sel3(rep, B1, bs.b1);
+    bs.b2 = sel3(rep, B2, bs.b2);
+    bs.b3 = sel3(rep, B3, bs.b3);
 }
 
 // Bits 0..7 of x spread to bits 0, 4, ..., 28.
