@@ -585,12 +585,15 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                 // 31 of Z & ~(Z + bs), shifted into the alive mask.
                 DT dm = 0;
                 if (wave_any(ncont)) {
+                    // That run reaches bit 31 exactly when Z + bs carries out
+                    // of it; the carries are shifted in as they come.
                     uint32_t lo = 0, hi = 0;
 #pragma unroll
                     for (int d = DL - 1; d >= 0; --d) {
-                        const uint32_t run = M[d] & ~(M[d] + bs);
-                        if (d >= 32) hi = funnel(hi, run, 31);
-                        else lo = funnel(lo, run, 31);
+                        uint32_t sum;
+                        const uint32_t cy = __builtin_add_overflow(M[d], bs, &sum) ? 1u : 0u;
+                        if (d >= 32) hi = hi + hi + cy;
+                        else lo = lo + lo + cy;
                     }
                     const DT alive = (DT)lo | (sizeof(DT) > 4 ? (DT)((uint64_t)hi << 32) : (DT)0);
                     constexpr DT all = (DL >= 8 * (int)sizeof(DT)) ? ~(DT)0 : (((DT)1 << DL) - 1);
