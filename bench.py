@@ -91,19 +91,134 @@ def time_steps(fn, steps, warmup):
     return per, t0.elapsed_time(t1), wall
 
 
-def traffic_record(kernel_src: str, key: str):
+# A kernel's sources: its file and the device headers it includes.  A traffic
+# record holds their hash and is used only while it matches.
+KERNEL_SOURCES = {"snake_chunk": ("filter.hip", "paf_tile.h", "paf_map.h", "paf_internal.h"),
+                  "key_levels": ("mlp.hip", "paf_map.h", "paf_internal.h")}
+
+
+def kernel_source_hash(kernel: str = "snake_chunk") -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_1910_03936_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(key: str):
     """HBM bytes per launch measured with rocprofv3 counters, if they were taken
-    on the current kernel source (else None)."""
+    on the current kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
     r = rec.get(key)
-    if not r or r.get("kernel_sha256_16") != h:
+    if not r or r.get("kernel_sha256_16") != kernel_source_hash():
         return None
     return r
+
+
+def counter_run(args):
+    """One kind of launch, repeated, for rocprofv3 counter runs: `plain` is the
+    compacting filter alone; `keyed` trains the cost model on --train-pairs
+    pairs, then runs the cost levels and the keyed filter in turn.  Every
+    dispatch of the chosen kernels in such a run is the record's launch."""
+    import torch
+
+    import pairgen
+    import paper_1910_03936_amd as paf
+    from paper_1910_03936_amd import costmodel
+
+    dev = torch.device("cuda", 0)
+    ctx = paf.Context(0)
+    w = pairgen.FIXED_250BP.with_E(args.E)
+    n = args.pairs or w.n_pairs
+    batch, _ = build_batch(ctx, w, n, dev)
+    out = ctx.alloc_out(n, paf.SNEAKYSNAKE, dev)
+    if args.counter_run == "plain":
+        step = lambda: ctx.filter(batch, paf.SNEAKYSNAKE, out=out)
+    else:
+        costmodel.train(ctx, w, n=args.train_pairs, epochs=4, batch=4096, lr=2e-3)
+        step = lambda: ctx.filter_keyed(batch, ctx.cost_levels(batch), out=out)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ctx.check()
+    print(json.dumps({"counter_run": args.counter_run, "n_pairs": n, "E": args.E, "launches": args.steps}),
+          flush=True)
+
+
+def _counter_csv(path):
+    """Per-dispatch counter sums of a rocprofv3 --pmc output folder:
+    {dispatch id: (kernel name, {counter: value})}."""
+    import csv
+    import glob
+
+    files = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+    if len(files) != 1:
+        raise SystemExit(f"expected one counter_collection.csv under {path}, found {len(files)}")
+    out = {}
+    with open(files[0]) as f:
+        for r in csv.DictReader(f):
+            d = int(r["Dispatch_Id"])
+            name, vals = out.setdefault(d, (r["Kernel_Name"], {}))
+            vals[r["Counter_Name"]] = vals.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def record_traffic(args):
+    """Writes profiles/hbm_traffic.json from counter runs under DIR:
+    plain_fetch, plain_write, plain_valu, keyed_fetch, keyed_write,
+    keyed_valu (bench.py --counter-run plain|keyed under rocprofv3 --pmc
+    FETCH_SIZE / WRITE_SIZE / the SQ counters), and cfetch, cwrite (the same
+    counters over bench.py --calibrate-copy).  FETCH_SIZE and WRITE_SIZE are
+    KiB per dispatch; each is scaled by the ratio of the copy's true bytes to
+    what the counter reads for it."""
+    d = args.record_traffic
+    n = args.pairs or 10_000_000
+    gib = 2 << 30
+    fs = gib / (max(v["FETCH_SIZE"] for _, v in _counter_csv(os.path.join(d, "cfetch")).values()) * 1024)
+    ws = gib / (max(v["WRITE_SIZE"] for _, v in _counter_csv(os.path.join(d, "cwrite")).values()) * 1024)
+    kernels = {"snake_chunk": f"chunk_kernel<{args.E}, false, false, 1>", "key_levels": f"key_kernel<{args.E}>"}
+    rec = {}
+
+    def mean(kind, part, kname):
+        rows = [v for name, v in _counter_csv(os.path.join(d, f"{kind}_{part}")).values()
+                if kname + "(" in name]
+        if not rows:
+            return None, 0
+        return {k: sum(r.get(k, 0.0) for r in rows) / len(rows) for k in rows[0]}, len(rows)
+
+    for kind in ("plain", "keyed"):
+        for label, kname in kernels.items():
+            if label == "key_levels" and kind == "plain":
+                continue
+            fv, nd = mean(kind, "fetch", kname)
+            wv, _ = mean(kind, "write", kname)
+            vv, _ = mean(kind, "valu", kname)
+            if fv is None or wv is None or vv is None:
+                raise SystemExit(f"no {kname} dispatches in the {kind} counter runs")
+            fb, wb = fv["FETCH_SIZE"] * 1024 * fs, wv["WRITE_SIZE"] * 1024 * ws
+            key = f"{label}_{kind}_250bp_E{args.E}" if label == "snake_chunk" else f"{label}_250bp_E{args.E}"
+            rec[key] = {"kernel_sha256_16": kernel_source_hash(label), "kernel": kname, "n_pairs": n,
+                        "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                        "bytes_per_launch": fb + wb, "fetch_scale": fs, "write_scale": ws, "dispatches": nd,
+                        "waves_per_launch": vv["SQ_WAVES"],
+                        "valu_insts_per_launch": vv["SQ_INSTS_VALU"],
+                        "valu_lane_util": vv["SQ_THREAD_CYCLES_VALU"] / (64 * vv["SQ_ACTIVE_INST_VALU"]),
+                        "mfma_insts_per_launch": vv.get("SQ_INSTS_MFMA", 0.0),
+                        "wait_per_wave_cycle": vv["SQ_WAIT_ANY"] / vv["SQ_WAVE_CYCLES"],
+                        "gui_active_cycles_per_xcd": vv["GRBM_GUI_ACTIVE"] / 8}
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    for k, r in rec.items():
+        log(f"{k}: {r['dispatches']} dispatches, fetch {r['fetch_bytes_per_launch'] / 1e9:.4f} GB, write "
+            f"{r['write_bytes_per_launch'] / 1e9:.4f} GB, VALU {r['valu_insts_per_launch']:.4g}, lanes "
+            f"{r['valu_lane_util']:.3f}, wait {r['wait_per_wave_cycle']:.3f}")
+    log(f"copy scale: fetch x {fs:.4f}, write x {ws:.4f}; wrote {path}")
 
 
 def cpu_model() -> str:
@@ -268,7 +383,14 @@ def main():
     ap.add_argument("--calibrate-valu", action="store_true",
                     help="only measure the VALU issue rate of known instruction mixes and print it")
     ap.add_argument("--reps", type=int, default=3, help="timed repetitions of each calibration kernel")
+    ap.add_argument("--counter-run", choices=["plain", "keyed"], default=None,
+                    help="only launch one kind of filter step --steps times (for rocprofv3 counter runs)")
+    ap.add_argument("--record-traffic", metavar="DIR", default=None,
+                    help="write profiles/hbm_traffic.json from the counter runs under DIR (no GPU)")
     args = ap.parse_args()
+    if args.record_traffic:
+        record_traffic(args)
+        return
     if args.calibrate_copy:
         calibrate_copy()
         return
@@ -282,6 +404,10 @@ def main():
         for k, v in r.items():
             log(f"{k:40s} " + "  ".join(f"{w} waves/SIMD: {g:7.1f} G/s" for w, g in v.items()))
         print(json.dumps({"valu_wave_instr_per_s_G": r, "model_line_G": VALU_PEAK_GIPS}), flush=True)
+        return
+
+    if args.counter_run:
+        counter_run(args)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -335,7 +461,7 @@ def main():
 
     def roof(kern_ms, bytes_pair, kernel, key):
         achieved = n * bytes_pair / (kern_ms / 1e3) / 1e9
-        tr = traffic_record(os.path.join(ROOT, "paper_1910_03936_amd", "csrc", "filter.hip"), key)
+        tr = traffic_record(key)
         r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": round(achieved / HBM_PEAK_GBS, 4),
              "traffic": None if tr is None else tr["bytes_per_launch"] * n / tr["n_pairs"],
