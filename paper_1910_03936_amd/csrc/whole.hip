@@ -11,17 +11,6 @@ namespace {
 // ---------------------------------------------------------------------------
 // Whole-map engine.
 
-// GateKeeper's amendment of one window word (Ch. 5, Sec. 5.2.2; SRS of
-// Sec. 3.2.1): a zero inside a streak of one or two zeros bounded by ones on
-// both sides becomes one.  L1/L2 are the bits one/two columns to the left,
-// R1/R2 to the right (taken from the neighbouring windows).
-__device__ __forceinline__ uint32_t amend_word(uint32_t g, uint32_t prev, uint32_t next) {
-    const uint32_t L1 = funnel(g, prev, 31);
-    const uint32_t L2 = funnel(g, prev, 30);
-    const uint32_t R1 = funnel(next, g, 1);
-    const uint32_t R2 = funnel(next, g, 2);
-    return g | (L1 & (R1 | R2)) | (R1 & (L1 | L2));
-}
 
 // Shouji: bit-sliced best 4-column segment per window start column.
 struct ShoujiBest {
@@ -134,14 +123,40 @@ __device__ __forceinline__ void build_blocked(const WindowWords& q, uint32_t* Mh
     }
 }
 
-// Only GateKeeper's map: vacant and past-end cells 0.
-template <int EMAX, int I = 0>
+// Window k of every active lane's pair is inner: k >= 1 and its columns,
+// plus max_E beyond, lie before the pair's end, so no cell of any diagonal
+// is vacant there.
+template <int EMAX>
+__device__ __forceinline__ bool inner_window(bool active, uint32_t k, uint32_t m) {
+    return !wave_any(active && (k == 0u || 32u * (k + 1u) + (uint32_t)EMAX > m));
+}
+
+// Only GateKeeper's map: vacant and past-end cells 0 (INNER: an inner window,
+// the raw mismatch words).
+template <int EMAX, bool INNER = false, int I = 0>
 __device__ __forceinline__ void build_gk(const WindowWords& q, uint32_t* G) {
     if constexpr (I < 2 * EMAX + 1) {
         constexpr int d = I - EMAX;
-        G[I] = diag_raw<d>(q) & ~(diag_vacant<d>(q) | q.vc);
-        build_gk<EMAX, I + 1>(q, G);
+        if constexpr (INNER) G[I] = diag_raw<d>(q);
+        else G[I] = diag_raw<d>(q) & ~(diag_vacant<d>(q) | q.vc);
+        build_gk<EMAX, INNER, I + 1>(q, G);
     }
+}
+
+// Fw AND GateKeeper's amendment of one window word g (Ch. 5, Sec. 5.2.2; SRS
+// of Sec. 3.2.1): a zero inside a streak of one or two zeros bounded by ones
+// on both sides becomes one.  L1/L2 are the bits one/two columns to the left,
+// R1/R2 to the right (taken from the neighbouring windows); the amended word
+// g | L1 (R1 | R2) | R1 (L1 | L2) = L1 (R1 | R2) | (R1 L2 | g) takes three
+// 3-input operations with the AND.
+__device__ __forceinline__ uint32_t and_amended(uint32_t Fw, uint32_t g, uint32_t prev, uint32_t next) {
+    const uint32_t L1 = funnel(g, prev, 31);
+    const uint32_t L2 = funnel(g, prev, 30);
+    const uint32_t R1 = funnel(next, g, 1);
+    const uint32_t R2 = funnel(next, g, 2);
+    const uint32_t t = __builtin_amdgcn_bitop3_b32(L1, R1, R2, 0xE0);  // L1 & (R1 | R2)
+    const uint32_t u = __builtin_amdgcn_bitop3_b32(R1, L2, g, 0xEA);   // (R1 & L2) | g
+    return __builtin_amdgcn_bitop3_b32(Fw, t, u, 0xE0);                // Fw & (t | u)
 }
 
 // FS: the decision stages this instantiation runs (bits of PAF_*), or 0 for
@@ -200,11 +215,13 @@ __device__ void whole_tile(const FilterParams& P, uint64_t tile, int lane, uint6
         // Above max_E 10 the third array would cost occupancy.
         uint32_t Gx[D];
         auto gk_window = [&](uint32_t w, const uint32_t (&Gpv)[D], const uint32_t (&Gcu)[D], uint32_t (&Gnx)[D]) {
+            const bool inner = inner_window<EMAX>(ps.valid && w < ps.W, w + 1u, m);
             if (ps.valid && w < ps.W) {
                 const uint32_t colpast = vacant_word((int)w, (int)m);  // columns >= m
                 gk_ham += popc(Gcu[EMAX] & ~colpast);
                 const WindowWords qn = window_words(rdL, rfL, lane, (int)w + 1, P.wmax, (int)m);
-                build_gk<EMAX>(qn, Gnx);
+                if (inner) build_gk<EMAX, true>(qn, Gnx);
+                else build_gk<EMAX>(qn, Gnx);
                 uint32_t Fw = ~0u;
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
@@ -212,7 +229,7 @@ __device__ void whole_tile(const FilterParams& P, uint64_t tile, int lane, uint6
                         const int d = i - EMAX;
                         if ((uint32_t)(d < 0 ? -d : d) > E) Gnx[i] = ~0u;
                     }
-                    Fw &= amend_word(Gcu[i], Gpv[i], Gnx[i]);
+                    Fw = and_amended(Fw, Gcu[i], Gpv[i], Gnx[i]);
                 }
                 gk_cnt += popc(Fw & ~colpast);
             }
@@ -255,7 +272,7 @@ __device__ void whole_tile(const FilterParams& P, uint64_t tile, int lane, uint6
                     }
                 }
                 if constexpr (needG) {
-                    if (doGK) Fw &= amend_word(Gc[i], Gp[i], Gn[i]);
+                    if (doGK) Fw = and_amended(Fw, Gc[i], Gp[i], Gn[i]);
                     Gp[i] = Gc[i];
                     Gc[i] = Gn[i];
                 }
