@@ -83,15 +83,16 @@ __device__ __forceinline__ void shouji_nibbles(const ShoujiBest& bs, uint32_t* n
 // Sequential store into the Shouji bit-vector for the 32 windows starting in
 // this window (Sec. 6.2.2): the best segment overwrites the vector's four
 // bits when it holds strictly more zeros.  S covers columns [32w, 32w+64).
+// Window starts past the pair's end hold segment 1111 (see below), which
+// never holds strictly more zeros than the vector, so they store nothing.
 template <int J = 0>
-__device__ __forceinline__ void shouji_store_nib(const uint32_t* nib, uint32_t& S_lo, uint32_t& S_hi,
-                                                 uint32_t ncols) {
+__device__ __forceinline__ void shouji_store_nib(const uint32_t* nib, uint32_t& S_lo, uint32_t& S_hi) {
     if constexpr (J < 32) {
         const uint32_t V = (nib[J >> 3] >> (4 * (J & 7))) & 0xFu;
         uint32_t cur;
         if constexpr (J <= 28) cur = (S_lo >> J) & 0xFu;
         else cur = funnel(S_hi, S_lo, J) & 0xFu;
-        const bool take = (uint32_t)J < ncols && popc(V) < popc(cur);
+        const bool take = popc(V) < popc(cur);
         if constexpr (J <= 28) {
             const uint32_t nlo = (S_lo & ~(0xFu << J)) | (V << J);
             S_lo = take ? nlo : S_lo;
@@ -101,7 +102,7 @@ __device__ __forceinline__ void shouji_store_nib(const uint32_t* nib, uint32_t& 
             S_lo = take ? nlo : S_lo;
             S_hi = take ? nhi : S_hi;
         }
-        shouji_store_nib<J + 1>(nib, S_lo, S_hi, ncols);
+        shouji_store_nib<J + 1>(nib, S_lo, S_hi);
     }
 }
 
@@ -283,10 +284,16 @@ __device__ void whole_tile(const FilterParams& P, uint64_t tile, int lane, uint6
             }
             if (doGK) gk_cnt += popc(Fw & ~colpast);
             if (doSH) {
+                // Start columns at or past the pair's end get segment 1111.
                 const uint32_t ncols = m - 32u * w;  // >= 1
+                const uint32_t past = ncols >= 32u ? 0u : ~0u << ncols;
+                bs.b0 |= past;
+                bs.b1 |= past;
+                bs.b2 |= past;
+                bs.b3 |= past;
                 uint32_t nib[4];
                 shouji_nibbles(bs, nib);
-                shouji_store_nib(nib, S_lo, S_hi, ncols);
+                shouji_store_nib(nib, S_lo, S_hi);
                 sh_cnt += popc(S_lo & ~colpast);
                 S_lo = S_hi;
                 S_hi = ~0u;
