@@ -66,6 +66,17 @@ def build_batch(ctx, w, n, dev, chunk=2_000_000):
     return b, first
 
 
+def ramp(fn, seconds=0.3):
+    """Untimed launches of fn for a few hundred ms: the GPU's clocks ramp up
+    under load, and a timed region should not start while they do."""
+    import torch
+
+    t = time.perf_counter()
+    while time.perf_counter() - t < seconds:
+        fn()
+        torch.cuda.synchronize()
+
+
 def time_steps(fn, steps, warmup):
     """Per-step HIP event times (ms) on the current stream, plus the total."""
     import torch
@@ -445,10 +456,7 @@ def main():
     # Plain batched filter.  The GPU's clocks ramp up under load: run the
     # filter untimed for a few hundred ms before the first timed region.
     out = ctx.alloc_out(n, SS, dev)
-    t = time.perf_counter()
-    while time.perf_counter() - t < 0.3:
-        ctx.filter(batch, SS, out=out)
-        torch.cuda.synchronize()
+    ramp(lambda: ctx.filter(batch, SS, out=out))
     per, total_ms, _ = time_steps(lambda: ctx.filter(batch, SS, out=out), args.steps, args.warmup)
     ctx.check()
     plain_ms = total_ms / args.steps
@@ -497,6 +505,9 @@ def main():
         # The learned pipeline: model levels, then the compacting filter with
         # each chunk ordered by them (one graph).
         out_l = ctx.alloc_out(n, SS, dev)
+        # The same untimed ramp as the plain filter's (training leaves the
+        # GPU idle for a while).
+        ramp(lambda: ctx.filter_bucketed_local(batch, out=out_l))
         per_l, total_l, _ = time_steps(lambda: ctx.filter_bucketed_local(batch, out=out_l), args.steps,
                                        args.warmup)
         ctx.check()
@@ -505,8 +516,10 @@ def main():
         learned_value = n / (learned_ms / 1e3)
         # Its two stages, each launched and timed on its own.
         key = ctx.cost_levels(batch)
+        ramp(lambda: ctx.cost_levels(batch))
         per_m, _, _ = time_steps(lambda: ctx.cost_levels(batch), args.steps, 1)
         out_k = ctx.alloc_out(n, SS, dev)
+        ramp(lambda: ctx.filter_keyed(batch, key, out=out_k))
         per_k, _, _ = time_steps(lambda: ctx.filter_keyed(batch, key, out=out_k), args.steps, 1)
         model_ms, keyed_ms = sum(per_m) / len(per_m), sum(per_k) / len(per_k)
         hist = torch.bincount(key.to(torch.int64), minlength=16)
@@ -712,6 +725,7 @@ def other_workload(args):
         out = ctx.alloc_out(n, SS, torch.device("cuda", 0))
 
         def timed(fn):
+            ramp(fn)
             per, tot, _ = time_steps(fn, args.steps, args.warmup)
             ctx.check()
             return tot / args.steps, sum(per) / len(per)
