@@ -116,10 +116,10 @@ def kernel_source_hash(kernel: str = "snake_chunk") -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_record(key: str):
+def traffic_record(key: str, path: str | None = None):
     """HBM bytes per launch measured with rocprofv3 counters, if they were taken
     on the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    path = path or os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -179,7 +179,7 @@ def _counter_csv(path):
 
 
 def record_traffic(args):
-    """Writes profiles/hbm_traffic.json from counter runs under DIR:
+    """Writes profiles/hbm_traffic.json (or --record-out) from counter runs under DIR:
     plain_fetch, plain_write, plain_valu, keyed_fetch, keyed_write,
     keyed_valu (bench.py --counter-run plain|keyed under rocprofv3 --pmc
     FETCH_SIZE / WRITE_SIZE / the SQ counters), and cfetch, cwrite (the same
@@ -221,7 +221,7 @@ def record_traffic(args):
                         "mfma_insts_per_launch": vv.get("SQ_INSTS_MFMA", 0.0),
                         "wait_per_wave_cycle": vv["SQ_WAIT_ANY"] / vv["SQ_WAVE_CYCLES"],
                         "gui_active_cycles_per_xcd": vv["GRBM_GUI_ACTIVE"] / 8}
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    path = args.record_out or os.path.join(ROOT, "profiles", "hbm_traffic.json")
     with open(path, "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")
@@ -398,6 +398,8 @@ def main():
                     help="only launch one kind of filter step --steps times (for rocprofv3 counter runs)")
     ap.add_argument("--record-traffic", metavar="DIR", default=None,
                     help="write profiles/hbm_traffic.json from the counter runs under DIR (no GPU)")
+    ap.add_argument("--record-out", metavar="PATH", default=None,
+                    help="where --record-traffic writes (default profiles/hbm_traffic.json)")
     args = ap.parse_args()
     if args.record_traffic:
         record_traffic(args)
