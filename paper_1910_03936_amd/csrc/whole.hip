@@ -255,6 +255,8 @@ __device__ void whole_tile(const FilterParams& P, uint64_t tile, int lane, uint6
             // mismatches, vacant cells not counted).
             if constexpr (needG)
                 if (doGK) gk_ham += popc(Gc[EMAX] & ~colpast);
+            // This window's blocked main diagonal (Shouji at E = 0, below).
+            const uint32_t mc0 = needM ? Mc[0] : 0u;
             // Next window's maps, then GateKeeper and Shouji per diagonal.
             const WindowWords qn = window_words(rdL, rfL, lane, (int)w + 1, P.wmax, (int)m);
             uint32_t Fw = ~0u;
@@ -278,12 +280,22 @@ __device__ void whole_tile(const FilterParams& P, uint64_t tile, int lane, uint6
                     Gc[i] = Gn[i];
                 }
                 if constexpr (needM) {
-                    if (doSH) shouji_candidate(bs, Mc[i], Mn[i], i == 0);
+                    if constexpr (EMAX > 0)
+                        if (doSH) shouji_candidate(bs, Mc[i], Mn[i], i == 0);
                     Mc[i] = Mn[i];
                 }
             }
             if (doGK) gk_cnt += popc(Fw & ~colpast);
-            if (doSH) {
+            if (doSH && EMAX == 0) {
+                // One diagonal (E = 0): the window starting at column j
+                // replaces the vector's bits j..j+3, which hold the diagonal's
+                // bits j..j+2 and a still unset 1 at j+3, exactly when bit j+3
+                // of the diagonal is 0; the first window leaves the vector's
+                // first four bits equal to the diagonal's either way.  So the
+                // vector ends equal to the diagonal, and the count is its
+                // Hamming distance.
+                sh_cnt += popc(mc0 & ~colpast);
+            } else if (doSH) {
                 // Start columns at or past the pair's end get segment 1111.
                 const uint32_t ncols = m - 32u * w;  // >= 1
                 const uint32_t past = ncols >= 32u ? 0u : ~0u << ncols;
