@@ -129,6 +129,24 @@ def test_edge_cases(gpu_ctx):
     gpu_ctx.check()
 
 
+def test_edge_cases_E0(gpu_ctx):
+    """The one-diagonal kernels (max_E 0; Shouji's count there in closed
+    form) on the edge lengths 1..512: each filter alone and all three."""
+    rows = [r for r in _edge_pairs() if r[3] == 0]
+    n = len(rows)
+    R = np.zeros((n, 512), np.uint8)
+    F = np.zeros((n, 512), np.uint8)
+    L = np.zeros(n, np.uint16)
+    for i, (a, b, m, E) in enumerate(rows):
+        R[i, :m], F[i, :m], L[i] = a, b, m
+    p = pairgen.Pairs(R, F, L, np.zeros(n, np.uint8), np.zeros(n, np.uint8), np.zeros(n, np.uint16))
+    want = oracle_for(p, ALL)
+    b = to_device(p, gpu_ctx, per_pair=True, offsets=True, max_len=512, max_E=0)
+    for f in (SS, GK, SH, GK | SH, ALL):
+        assert_parity(results(gpu_ctx.filter(b, f), n), {k: want[k] for k in want if k & f}, f"E=0 mask {f}")
+    gpu_ctx.check()
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 65])
 def test_tiny_batches(gpu_ctx, n):
     p = pairgen.generate(pairgen.FIXED_250BP, 100, n)
