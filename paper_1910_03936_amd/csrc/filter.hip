@@ -695,8 +695,12 @@ __host__ __device__ constexpr size_t chunk_wave_bytes_t(uint32_t K, bool keyed) 
 
 // Up to EMAX 8 the kernel is held to the registers of five waves per SIMD:
 // measured faster than four waves with the registers it would take otherwise.
+// At EMAX 20 and 31 four waves with a few spilled registers measured faster
+// than three without (1.28 -> 1.22 and 2.42 -> 2.21 ms per 10M pairs of
+// 250 bp); at 25 they did not (1.64 either way), nor are they needed up to 15.
 template <int EMAX, bool GENERAL, bool PART, int LPP>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(LPP == 2 ? 4 : (EMAX <= 8 ? 5 : 1))))
+__global__ void __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu(LPP == 2 ? 4 : (EMAX <= 8 ? 5 : ((EMAX == 20 || EMAX == 31) ? 4 : 1)))))
 chunk_kernel(FilterParams P) {
     extern __shared__ uint64_t lds[];
     using DT = typename ChunkDead<EMAX, LPP>::T;
