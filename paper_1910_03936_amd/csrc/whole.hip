@@ -11,6 +11,7 @@ namespace {
 // ---------------------------------------------------------------------------
 // Whole-map engine.
 
+
 // Shouji: bit-sliced best 4-column segment per window start column.
 struct ShoujiBest {
     uint32_t o0, o1, o2;      // ones in the best segment (bit-sliced, 0..4)
