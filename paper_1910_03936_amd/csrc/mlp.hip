@@ -407,6 +407,29 @@ __device__ __forceinline__ FeatWords feat_words(const FilterParams& P, uint64_t 
     return q;
 }
 
+// The words of pair p of a batch with one length and one threshold (`ok`:
+// both in range), loaded without a branch: a lane past the batch reads pair
+// 0's words, and a word at or past the pair's W repeats its word 0 (the
+// feature code reads only words below W).  With no branch around them, the
+// loads of later tiles stay in flight while earlier tiles are worked on.
+__device__ __forceinline__ FeatWords feat_words_uniform(const FilterParams& P, uint64_t p, bool ok) {
+    FeatWords q;
+    q.valid = ok && p < P.n_pairs;
+    q.m = P.uniform_len;
+    q.E = P.uniform_E;
+    const uint32_t W = ok ? (q.m + 31) >> 5 : 1u;
+    const uint64_t off = (q.valid ? p : 0ull) * (uint64_t)P.stride_words;
+    const uint64_t* rd = P.reads + off;
+    const uint64_t* rf = P.refs + off;
+    const uint32_t k1 = W > 1 ? 1u : 0u, k2 = W > 2 ? 2u : 0u;
+    q.r0 = rd[0];
+    q.r1 = rd[k1];
+    q.r2 = rd[k2];
+    q.f0 = rf[0];
+    q.f1 = rf[k1];
+    return q;
+}
+
 template <int EF, int NF>
 __device__ __forceinline__ void features_from_words(const FeatWords& w, float* f, bool all_long,
                                                     bool masked, bool* gate) {
@@ -421,7 +444,12 @@ __device__ __forceinline__ void features_from_words(const FeatWords& w, float* f
 // two (the other 32 inputs are zero and add nothing).  Up to 18 per side
 // they fit 40 slots: still two k-tiles, but the staged rows (and so the
 // rows a gated wave can hold) stay small.
-template <int EF>
+//
+// UNIFORM (gated launches on batches with no per-pair lengths, thresholds or
+// offsets): each wave keeps two tiles of words in flight, in two register
+// sets used in turn (a copy from one set to the other would wait for its
+// loads), and computes layer 2 in two halves to make room for them.
+template <int EF, bool UNIFORM>
 __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
     // Staged inputs per pair: the 2 EF + 3 non-zero ones in 32 or 40 slots
     // (compact), else the model's 64.
@@ -439,6 +467,7 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
     __shared__ __attribute__((aligned(16))) uint16_t sX[kKeyWaves][ROWS][NF + 8];
     __shared__ uint64_t sIdx[kKeyWaves][CK ? 128 : 1];
     const FilterParams& P = K.P;
+    if (P.n_tiles == 0) return;
     if constexpr (CK) {
         // Fragment order: lane (q, g) of m-tile mt, k-tile kt holds
         // W1[16 mt + q][input of compact slot 32 kt + 8 g + j], j = 0..7.
@@ -461,7 +490,7 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
     }
     const float b3 = K.master[OFF_B3];
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int q16 = lane & 15, grp = lane >> 4;
     const uint32_t stride = gridDim.x * kKeyWaves;
     // Gated (compact layout, in-chunk levels only): the wave collects the
@@ -472,8 +501,20 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
     const bool gated = CK && K.gate != 0u;
     uint32_t n_buf = 0;
     uint32_t tile = blockIdx.x * kKeyWaves + wave;
-    FeatWords cur = feat_words(P, (uint64_t)tile * 64 + lane);
-    for (;;) {
+    // One length and threshold for the whole batch: checked once.
+    const bool uni_ok = P.uniform_len >= 1 && P.uniform_len <= P.max_len && P.uniform_E <= P.max_E;
+    if (UNIFORM && !uni_ok && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(P.err, 1u);
+    auto fetch = [&](uint32_t t) -> FeatWords {
+        if constexpr (UNIFORM)
+            return feat_words_uniform(P, (uint64_t)(t < P.n_tiles ? t : P.n_tiles - 1) * 64 + lane, uni_ok);
+        else
+            return feat_words(P, (uint64_t)t * 64 + lane);
+    };
+    // One tile: the features (and gate) of its pairs from the words in cur,
+    // which are then refilled with those of the tile `ahead` strides on; then
+    // the model on a full tile of staged rows, if there is one.  Returns
+    // false after the wave's last tile.
+    auto step = [&](FeatWords& cur, uint32_t ahead) -> bool {
         const bool have = tile < P.n_tiles;
         const uint64_t p = (uint64_t)tile * 64 + lane;
         uint32_t m = 0, E = 0;
@@ -488,7 +529,7 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
             } else {
                 float f[NF];
                 if (cur.valid) {
-                    features_from_words<EF, NF>(cur, f, all_long, masked, gated ? &pass : nullptr);
+                    features_from_words<EF, NF>(cur, f, all_long, masked, &pass);
                 } else {
 #pragma unroll
                     for (int i = 0; i < NF; ++i) f[i] = 0.0f;
@@ -513,8 +554,14 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
                 for (int c = 0; c < NF / 8; ++c) *reinterpret_cast<uint4*>(&sX[wave][r][8 * c]) = row[c];
             }
             // Next tile's words are fetched while this one goes through the model.
-            if (tile + stride < P.n_tiles) cur = feat_words(P, (uint64_t)(tile + stride) * 64 + lane);
+            if constexpr (!UNIFORM)
+                if (tile + stride < P.n_tiles) cur = fetch(tile + stride);
         }
+        // Uniform batches: the words of the tile `ahead` strides on, on every
+        // path (a fetch past the last tile reads the last tile's words again),
+        // so that every path into the next step has the same loads in flight
+        // and the wait before using a set of words covers only that set.
+        if constexpr (UNIFORM) cur = fetch(tile + ahead * stride);
         const uint32_t rows = gated ? (n_buf >= 64u ? 64u : (have ? 0u : n_buf)) : (have ? 64u : 0u);
         if (rows > 0) {
             wave_lds_sync();
@@ -528,10 +575,6 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
                     xf[kt][nt] = 32 * kt + 8 * grp < NF
                                      ? *reinterpret_cast<const bf16x8*>(&sX[wave][16 * nt + q16][32 * kt + 8 * grp])
                                      : bf16x8{};
-            f32x4 acc2[8][4];
-            // Layer 1 for the two m-tiles 2 kt2, 2 kt2 + 1 gives layer 2's operand
-            // B for k-tile kt2: relu(W1 x + b1) rounded to bf16 (ReLU applied to
-            // the packed bf16 pair as a 16-bit integer max: rounding keeps signs).
             auto layer1 = [&](int kt2, bf16x8* b2) {
 #pragma unroll
                 for (int half = 0; half < 2; ++half) {
@@ -557,41 +600,97 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
                         }
                 }
             };
-            {
-                // k-tile 0: the accumulators start from the bias (C operand).
-                bf16x8 b2[4];
-                layer1(0, b2);
-#pragma unroll
-                for (int mt2 = 0; mt2 < 8; ++mt2) {
-                    const f32x4 bias2 = *reinterpret_cast<const f32x4*>(&sB2[16 * mt2 + 4 * grp]);
-                    const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(&sW2[((mt2 * 4 + 0) * 64 + lane) * 8]);
-#pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) acc2[mt2][nt] = mfma(a2, b2[nt], bias2);
-                }
-            }
-#pragma unroll 1
-            for (int kt2 = 1; kt2 < 4; ++kt2) {
-                bf16x8 b2[4];
-                layer1(kt2, b2);
-#pragma unroll
-                for (int mt2 = 0; mt2 < 8; ++mt2) {
-                    const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(&sW2[((mt2 * 4 + kt2) * 64 + lane) * 8]);
-#pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) acc2[mt2][nt] = mfma(a2, b2[nt], acc2[mt2][nt]);
-                }
-            }
-            // Head: y = w3 . relu(layer 2) + b3; lane l ends with row l.
             float yv = 0.0f;
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                float t = 0.0f;
-#pragma unroll
-                for (int mt2 = 0; mt2 < 8; ++mt2)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) t += sW3[16 * mt2 + 4 * grp + i] * relu_bits(acc2[mt2][nt][i]);
-                t += __shfl_xor(t, 16);
-                t += __shfl_xor(t, 32);
-                if (grp == nt) yv = t;
+            if constexpr (UNIFORM) {
+                // Layer 2 and the head in two halves of the 128 hidden units (m-tiles
+                // 0..3, then 4..7), recomputing layer 1 for the second: half the
+                // accumulators, so a wave keeps registers for more words in flight.
+                // Each head sum takes its terms in the same order as over all eight
+                // m-tiles at once (m-tile, then element), so the result is the same.
+                float th[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    #pragma unroll 1
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    f32x4 acc2[4][4];
+                    {
+                        // k-tile 0: the accumulators start from the bias (C operand).
+                        bf16x8 b2[4];
+                        layer1(0, b2);
+    #pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int mt2 = 4 * h2 + j;
+                            const f32x4 bias2 = *reinterpret_cast<const f32x4*>(&sB2[16 * mt2 + 4 * grp]);
+                            const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(&sW2[((mt2 * 4 + 0) * 64 + lane) * 8]);
+    #pragma unroll
+                            for (int nt = 0; nt < 4; ++nt) acc2[j][nt] = mfma(a2, b2[nt], bias2);
+                        }
+                    }
+    #pragma unroll 1
+                    for (int kt2 = 1; kt2 < 4; ++kt2) {
+                        bf16x8 b2[4];
+                        layer1(kt2, b2);
+    #pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int mt2 = 4 * h2 + j;
+                            const bf16x8 a2 =
+                                *reinterpret_cast<const bf16x8*>(&sW2[((mt2 * 4 + kt2) * 64 + lane) * 8]);
+    #pragma unroll
+                            for (int nt = 0; nt < 4; ++nt) acc2[j][nt] = mfma(a2, b2[nt], acc2[j][nt]);
+                        }
+                    }
+                    // Head: y = w3 . relu(layer 2) + b3.
+    #pragma unroll
+                    for (int nt = 0; nt < 4; ++nt)
+    #pragma unroll
+                        for (int j = 0; j < 4; ++j)
+    #pragma unroll
+                            for (int i = 0; i < 4; ++i)
+                                th[nt] += sW3[16 * (4 * h2 + j) + 4 * grp + i] * relu_bits(acc2[j][nt][i]);
+                }
+                // Lane l ends with row l.
+    #pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    float t = th[nt];
+                    t += __shfl_xor(t, 16);
+                    t += __shfl_xor(t, 32);
+                    if (grp == nt) yv = t;
+                }
+            } else {
+                f32x4 acc2[8][4];
+                {
+                    // k-tile 0: the accumulators start from the bias (C operand).
+                    bf16x8 b2[4];
+                    layer1(0, b2);
+    #pragma unroll
+                    for (int mt2 = 0; mt2 < 8; ++mt2) {
+                        const f32x4 bias2 = *reinterpret_cast<const f32x4*>(&sB2[16 * mt2 + 4 * grp]);
+                        const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(&sW2[((mt2 * 4 + 0) * 64 + lane) * 8]);
+    #pragma unroll
+                        for (int nt = 0; nt < 4; ++nt) acc2[mt2][nt] = mfma(a2, b2[nt], bias2);
+                    }
+                }
+    #pragma unroll 1
+                for (int kt2 = 1; kt2 < 4; ++kt2) {
+                    bf16x8 b2[4];
+                    layer1(kt2, b2);
+    #pragma unroll
+                    for (int mt2 = 0; mt2 < 8; ++mt2) {
+                        const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(&sW2[((mt2 * 4 + kt2) * 64 + lane) * 8]);
+    #pragma unroll
+                        for (int nt = 0; nt < 4; ++nt) acc2[mt2][nt] = mfma(a2, b2[nt], acc2[mt2][nt]);
+                    }
+                }
+                // Head: y = w3 . relu(layer 2) + b3; lane l ends with row l.
+    #pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    float t = 0.0f;
+    #pragma unroll
+                    for (int mt2 = 0; mt2 < 8; ++mt2)
+    #pragma unroll
+                        for (int i = 0; i < 4; ++i) t += sW3[16 * mt2 + 4 * grp + i] * relu_bits(acc2[mt2][nt][i]);
+                    t += __shfl_xor(t, 16);
+                    t += __shfl_xor(t, 32);
+                    if (grp == nt) yv = t;
+                }
             }
             const float y = yv + b3;
             if (gated) {
@@ -618,8 +717,24 @@ __global__ void __launch_bounds__(64 * kKeyWaves) key_kernel(KeyParams K) {
                 wave_lds_sync();
             }
         }
-        if (!have) break;
+        if (!have) return false;
         tile += stride;
+        return true;
+    };
+    if constexpr (UNIFORM) {
+        FeatWords a = fetch(tile), b = fetch(tile + stride);
+        for (;;) {
+            // Both steps run on every pass (a step past the wave's last tile
+            // only refills), so every path round the loop has issued the
+            // loads of both sets in the same order.
+            const bool more_a = step(a, 2u);
+            const bool more_b = step(b, 2u);
+            if (!(more_a && more_b)) break;
+        }
+    } else {
+        FeatWords a = fetch(tile);
+        while (step(a, 1u)) {
+        }
     }
 }
 
@@ -897,16 +1012,21 @@ __global__ void u16_to_f32_kernel(const uint16_t* a, uint64_t n, float* out) {
 
 template <int EF>
 const void* features_ptr() { return reinterpret_cast<const void*>(&features_kernel<EF>); }
+// The two-sets form up to 12 diagonals per side; above, its registers spill.
 template <int EF>
-const void* key_ptr() { return reinterpret_cast<const void*>(&key_kernel<EF>); }
+const void* key_ptr(bool two_sets) {
+    if constexpr (EF <= 12)
+        if (two_sets) return reinterpret_cast<const void*>(&key_kernel<EF, true>);
+    return reinterpret_cast<const void*>(&key_kernel<EF, false>);
+}
 
 // Diagonals the features use: min(E bucket, 30).
 int feature_ef(int emax) { return emax > 30 ? 30 : emax; }
 
-const void* feature_kernel_for(int ef, bool fused) {
+const void* feature_kernel_for(int ef, bool fused, bool two_sets = false) {
     switch (ef) {
 #define PAF_FCASE(X) \
-    case X: return fused ? key_ptr<X>() : features_ptr<X>();
+    case X: return fused ? key_ptr<X>(two_sets) : features_ptr<X>();
         PAF_FCASE(0) PAF_FCASE(1) PAF_FCASE(2) PAF_FCASE(3) PAF_FCASE(4) PAF_FCASE(5) PAF_FCASE(6)
         PAF_FCASE(7) PAF_FCASE(8) PAF_FCASE(10) PAF_FCASE(12) PAF_FCASE(15) PAF_FCASE(20) PAF_FCASE(25)
         PAF_FCASE(30)
@@ -991,7 +1111,10 @@ hipError_t launch_learned_buckets(const MlpDev& m, const FilterParams& p, int nu
                                   uint8_t* bucket, hipStream_t s, bool chunk_key) {
     const int emax = emax_bucket((int)p.max_E);
     if (emax < 0) return hipErrorInvalidValue;
-    const void* k = feature_kernel_for(feature_ef(emax), true);
+    // Gated launches of uniform batches take the two-sets form (the model
+    // runs on a third of the tiles there, so its halves cost little).
+    const bool two_sets = !p.len && !p.E && !p.word_offset && chunk_key && !pred;
+    const void* k = feature_kernel_for(feature_ef(emax), true, two_sets);
     if (!k) return hipErrorInvalidValue;
     KeyParams kp;
     kp.P = p;
