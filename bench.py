@@ -191,12 +191,15 @@ def record_traffic(args):
     gib = 2 << 30
     fs = gib / (max(v["FETCH_SIZE"] for _, v in _counter_csv(os.path.join(d, "cfetch")).values()) * 1024)
     ws = gib / (max(v["WRITE_SIZE"] for _, v in _counter_csv(os.path.join(d, "cwrite")).values()) * 1024)
-    kernels = {"snake_chunk": f"chunk_kernel<{args.E}, false, false, 1>", "key_levels": f"key_kernel<{args.E}>"}
+    # The levels kernel's second template argument picks its form (two tiles
+    # of words in flight on uniform batches); either form counts.
+    kernels = {"snake_chunk": (f"chunk_kernel<{args.E}, false, false, 1>(",),
+               "key_levels": (f"key_kernel<{args.E}>(", f"key_kernel<{args.E}, true>(", f"key_kernel<{args.E}, false>(")}
     rec = {}
 
-    def mean(kind, part, kname):
+    def mean(kind, part, knames):
         rows = [v for name, v in _counter_csv(os.path.join(d, f"{kind}_{part}")).values()
-                if kname + "(" in name]
+                if any(k in name for k in knames)]
         if not rows:
             return None, 0
         return {k: sum(r.get(k, 0.0) for r in rows) / len(rows) for k in rows[0]}, len(rows)
@@ -209,10 +212,10 @@ def record_traffic(args):
             wv, _ = mean(kind, "write", kname)
             vv, _ = mean(kind, "valu", kname)
             if fv is None or wv is None or vv is None:
-                raise SystemExit(f"no {kname} dispatches in the {kind} counter runs")
+                raise SystemExit(f"no {kname[0][:-1]} dispatches in the {kind} counter runs")
             fb, wb = fv["FETCH_SIZE"] * 1024 * fs, wv["WRITE_SIZE"] * 1024 * ws
             key = f"{label}_{kind}_250bp_E{args.E}" if label == "snake_chunk" else f"{label}_250bp_E{args.E}"
-            rec[key] = {"kernel_sha256_16": kernel_source_hash(label), "kernel": kname, "n_pairs": n,
+            rec[key] = {"kernel_sha256_16": kernel_source_hash(label), "kernel": kname[0][:-1], "n_pairs": n,
                         "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
                         "bytes_per_launch": fb + wb, "fetch_scale": fs, "write_scale": ws, "dispatches": nd,
                         "waves_per_launch": vv["SQ_WAVES"],

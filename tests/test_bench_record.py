@@ -16,7 +16,7 @@ import bench  # noqa: E402
 
 CHUNK = "void paf::(anonymous namespace)::chunk_kernel<10, false, false, 1>(paf::FilterParams)"
 LABEL = "void paf::(anonymous namespace)::chunk_kernel<31, false, false, 1>(paf::FilterParams)"
-KEY = "void paf::(anonymous namespace)::key_kernel<10>(paf::(anonymous namespace)::KeyParams)"
+KEY = "void paf::(anonymous namespace)::key_kernel<10, true>(paf::(anonymous namespace)::KeyParams)"
 COPY = "__amd_rocclr_copyBuffer"
 
 
