@@ -423,6 +423,27 @@ def test_cost_levels_match_predictions(gpu_ctx):
 
 
 @gpu
+def test_cost_levels_uniform_batches(gpu_ctx):
+    """Batches with one length and threshold take the levels kernel's
+    two-tiles-in-flight form: its keys against the ungated kernel's
+    predictions and the gate, at sizes of one tile, one tile and a pair, a
+    ragged tail, pairs shorter than 64 + E (the counting path), a threshold
+    below its bucket's (masked diagonals) and the form's largest bucket."""
+    from gpu_util import to_device
+    _set_random_model(gpu_ctx, seed=15)
+    for m, E, n in ((250, 10, 1), (250, 10, 64), (250, 10, 65), (250, 10, 130), (250, 10, 9001),
+                    (100, 5, 7777), (40, 3, 3000), (250, 9, 3000), (70, 12, 2000)):
+        w = pairgen.Workload(f"{m} bp, E {E}", n, (m,), 20, 0.5, fixed_E=E, seed=pairgen.SEED_BASE + 61 + m + E)
+        p = pairgen.generate(w, 0, n)
+        b = to_device(p, gpu_ctx, per_pair=False, offsets=False)
+        y = gpu_ctx.mlp_predict(b).cpu().numpy()
+        key = gpu_ctx.cost_levels(b).cpu().numpy().astype(np.int64)
+        want = np.where(model_gate_host(p), np.array([15 - chunk_level_host(v) for v in y]), 15)
+        assert np.array_equal(key, want), (m, E, n)
+    gpu_ctx.check()
+
+
+@gpu
 def test_filter_keyed_any_key(gpu_ctx):
     """Any key gives the plain outputs: random, constant, reversed, and the
     model's own levels."""
