@@ -444,6 +444,29 @@ def test_cost_levels_uniform_batches(gpu_ctx):
 
 
 @gpu
+def test_bucketed_local_uniform_batches(gpu_ctx):
+    """The learned pipeline on batches with one length and threshold (the
+    levels kernel's two-tiles-in-flight form, then the keyed filter) against
+    the oracle, captured and replayed."""
+    import paper_1910_03936_amd as paf
+    from gpu_util import to_device
+    SS = paf.SNEAKYSNAKE
+    _set_random_model(gpu_ctx, seed=16)
+    for m, E, n in ((250, 10, 9000), (250, 10, 65), (250, 0, 2001), (100, 5, 4001), (70, 12, 2000),
+                    (250, 9, 3000)):
+        w = pairgen.Workload(f"{m} bp, E {E}", n, (m,), 40, 0.7, fixed_E=E, seed=pairgen.SEED_BASE + 71 + m + E)
+        p = pairgen.generate(w, 0, n)
+        b = to_device(p, gpu_ctx, per_pair=False, offsets=False)
+        want = oracle.filter_batch(p.reads, p.refs, p.len, p.E, SS)[SS]
+        for rep in range(2):
+            got = gpu_ctx.filter_bucketed_local(b)
+            acc = paf.accept_bits_to_bool(got[SS][0], n).cpu().numpy().astype(np.uint8)
+            assert np.array_equal(acc, want[0]), (m, E, n, rep)
+            assert np.array_equal(paf.counts_u16(got[SS][1]).cpu().numpy(), want[1].astype(np.int64)), (m, E, n, rep)
+    gpu_ctx.check()
+
+
+@gpu
 def test_filter_keyed_any_key(gpu_ctx):
     """Any key gives the plain outputs: random, constant, reversed, and the
     model's own levels."""
