@@ -80,7 +80,13 @@ def test_full_size_fixed_250bp(gpu_ctx, fixed250, E):
     shared = results(gpu_ctx.filter(b, ALL), n)
     check_properties(shared, E)
     alone = results(gpu_ctx.filter(b, SS), n)[SS]
-    outs = [("compacting engine", alone[0], alone[1]), ("all stages in one call", shared[SS][0], shared[SS][1])]
+    # The learned pipeline (levels, then the undecided pairs of each chunk in
+    # level order) with the initial weights: the decisions never depend on
+    # the model.
+    gpu_ctx.mlp_set_params(pairgen.init_mlp_params())
+    learned = results(gpu_ctx.filter_bucketed_local(b), n)[SS]
+    outs = [("compacting engine", alone[0], alone[1]), ("all stages in one call", shared[SS][0], shared[SS][1]),
+            ("learned pipeline", learned[0], learned[1])]
     if E >= 8:
         # the whole-map kernel's SneakySnake (persistent launch, all stages)
         whole = results(gpu_ctx.filter_persistent(b, ALL), n)
