@@ -218,8 +218,7 @@ paf_status run_persistent(paf_ctx* ctx, FilterParams p, Engine eng, int emax, co
     p.chunk = compacting ? L.chunk_tiles : 0u;
     p.span0 = std::max(1u, L.first_pass_windows);
     p.span = std::max(1u, L.pass_windows);
-    sh.lds_bytes = compacting ? chunk_lds_bytes(L.waves_per_block, general, emax, L.chunk_tiles, L.lanes_per_pair,
-                                                p.order_key != nullptr)
+    sh.lds_bytes = compacting ? chunk_lds_bytes(L.waves_per_block, general, emax, L.chunk_tiles, L.lanes_per_pair)
                               : filter_lds_bytes(L.waves_per_block, p.wmax);
     if (sh.lds_bytes > 160 * 1024) return fail(PAF_ERR_RANGE, "layout needs more LDS than a CU has");
     PAF_HIP(allow_lds(k, sh.lds_bytes), "hipFuncSetAttribute");
@@ -556,7 +555,7 @@ paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, co
         p.span0 = std::max(1u, PL.first_pass_windows);
         p.span = std::max(1u, PL.pass_windows);
         sh.waves_per_block = PL.waves_per_block;
-        sh.lds_bytes = chunk_lds_bytes(sh.waves_per_block, general, emax, p.chunk, PL.lanes_per_pair, false);
+        sh.lds_bytes = chunk_lds_bytes(sh.waves_per_block, general, emax, p.chunk, PL.lanes_per_pair);
         if (sh.lds_bytes > 160 * 1024) return fail(PAF_ERR_RANGE, "layout needs more LDS than a CU has");
         units = (p.n_tiles + p.chunk - 1) / p.chunk;
     }
@@ -590,7 +589,7 @@ paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t
     p.span = std::max(1u, PL.pass_windows);
     LaunchShape sh;
     sh.waves_per_block = PL.waves_per_block;
-    sh.lds_bytes = chunk_lds_bytes(sh.waves_per_block, general, emax, p.chunk, 1, false);
+    sh.lds_bytes = chunk_lds_bytes(sh.waves_per_block, general, emax, p.chunk, 1);
     if (sh.lds_bytes > 160 * 1024) return fail(PAF_ERR_RANGE, "layout needs more LDS than a CU has");
     const uint64_t units = (p.n_tiles + p.chunk - 1) / p.chunk;
     sh.blocks = (uint32_t)((units + sh.waves_per_block - 1) / sh.waves_per_block);
@@ -753,8 +752,7 @@ paf_status paf_autotune(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, 
         for (uint32_t lpp : {1u, 2u}) {
             if (lpp == 2 && emax < 10) continue;
             for (uint32_t K : {4u, 6u, 8u, 16u}) {
-                // With the sort buffer: a tuned layout also serves the keyed launches.
-                const size_t lds = chunk_lds_bytes(wpb, true, emax, K, lpp, true);
+                const size_t lds = chunk_lds_bytes(wpb, true, emax, K, lpp);
                 if (lds > 160 * 1024) continue;
                 for (uint32_t sp : {1u, 2u}) {
                     cands.push_back(paf_layout{lpp, wpb, 0u, 1u, K, sp, sp});

@@ -259,15 +259,11 @@ template <typename DT, bool GENERAL>
 struct ChunkLds {
     uint64_t* ent;    // the list: K*64 entries
     uint64_t* off;    // GENERAL only: word offset of each pair of the chunk (by pair index)
-    uint64_t* stage;  // the keyed sort's buffer (kStageArea entries)
     DT* dead;         // dead-diagonal mask of each pair (by pair index; two halves, one per
                       // lane, with two lanes per pair)
     uint32_t* acc;    // 2K accept words (plain order)
     uint16_t* cnt;    // K*64 counts (plain order)
 };
-
-// Entries the keyed sort of the first pass's survivors can order in LDS.
-constexpr int kStageArea = 320;
 
 // The first pass's windows 0 and 1 read words 0..2 of the read and words 0
 // and 1 of the reference.  Each lane loads its own pair's five at the start
@@ -621,12 +617,13 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
             n_out += (uint32_t)__builtin_popcountll(bal);
         }
         n_ent = n_out;
-        if (first_pass && keyed && n_ent > 1 && n_ent <= (uint32_t)kStageArea) {
+        if (first_pass && keyed && n_ent > 1 && 2 * n_ent <= K * 64u) {
             // The undecided pairs enter the later passes grouped into four
             // classes by the key's bits 2-3 (a stable counting sort by wave
-            // ballots, through the staging area), so each group of 64 takes
-            // pairs of like predicted cost.  (More survivors than the area
-            // holds keep their order: the key only orders work.)
+            // ballots, into the list's unused tail and back), so each group of
+            // 64 takes pairs of like predicted cost.  (More survivors than
+            // half the list keep their order: the key only orders work.)
+            uint64_t* const stage = L.ent + (K * 64u - n_ent);
             wave_lds_sync();
             constexpr uint32_t NB = 4;
             uint32_t base[NB];
@@ -658,10 +655,10 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
                     if (cls == v) pos = base[v] + below;
                     base[v] += (uint32_t)__builtin_popcountll(mv);
                 }
-                if (cls < NB) L.stage[pos] = v64;
+                if (cls < NB) stage[pos] = v64;
             }
             wave_lds_sync();
-            for (uint32_t i = (uint32_t)lane; i < n_ent; i += 64) L.ent[i] = L.stage[i];
+            for (uint32_t i = (uint32_t)lane; i < n_ent; i += 64) L.ent[i] = stage[i];
         }
     }
     if (plain_out) {
@@ -684,13 +681,12 @@ __device__ void chunk_snake(const FilterParams& P, uint32_t chunk, uint32_t K, i
     }
 }
 
-// Bytes of one wave's LDS: list, offsets (general layout), staging / sort
-// area, dead masks, accept words and counts.
+// Bytes of one wave's LDS: list, offsets (general layout), dead masks,
+// accept words and counts.
 template <int EMAX, bool GENERAL, int LPP = 1>
-__host__ __device__ constexpr size_t chunk_wave_bytes_t(uint32_t K, bool keyed) {
+__host__ __device__ constexpr size_t chunk_wave_bytes_t(uint32_t K) {
     using DT = typename ChunkDead<EMAX, LPP>::T;
-    return (size_t)K * 64 * (8 + (GENERAL ? 8 : 0) + LPP * sizeof(DT) + 2) + (keyed ? (size_t)kStageArea * 8 : 0) +
-           (size_t)K * 8;
+    return (size_t)K * 64 * (8 + (GENERAL ? 8 : 0) + LPP * sizeof(DT) + 2) + (size_t)K * 8;
 }
 
 // Up to EMAX 8 the kernel is held to the registers of five waves per SIMD:
@@ -709,10 +705,7 @@ chunk_kernel(FilterParams P) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t K = P.chunk;
     const uint32_t NE = K * 64u;
-    // The sort buffer exists only in keyed launches (the others get the LDS
-    // back as occupancy).
-    const bool keyed = P.order_key != nullptr;
-    char* b = reinterpret_cast<char*>(lds) + (size_t)wave * chunk_wave_bytes_t<EMAX, GENERAL, LPP>(K, keyed);
+    char* b = reinterpret_cast<char*>(lds) + (size_t)wave * chunk_wave_bytes_t<EMAX, GENERAL, LPP>(K);
     ChunkLds<DT, GENERAL> L;
     L.ent = reinterpret_cast<uint64_t*>(b);
     b += (size_t)NE * 8;
@@ -722,8 +715,6 @@ chunk_kernel(FilterParams P) {
     } else {
         L.off = nullptr;
     }
-    L.stage = keyed ? reinterpret_cast<uint64_t*>(b) : nullptr;
-    b += keyed ? (size_t)kStageArea * 8 : 0;
     L.dead = reinterpret_cast<DT*>(b);
     b += (size_t)NE * LPP * sizeof(DT);
     L.acc = reinterpret_cast<uint32_t*>(b);
@@ -773,9 +764,9 @@ const void* chunk2_kernel_for(int emax) {
 }
 
 template <bool GENERAL>
-size_t chunk_bytes_for(int emax, uint32_t K, uint32_t lpp, bool keyed) {
-    if (lpp == 2) return chunk_wave_bytes_t<31, GENERAL, 2>(K, keyed);
-    return emax <= 15 ? chunk_wave_bytes_t<15, GENERAL>(K, keyed) : chunk_wave_bytes_t<31, GENERAL>(K, keyed);
+size_t chunk_bytes_for(int emax, uint32_t K, uint32_t lpp) {
+    if (lpp == 2) return chunk_wave_bytes_t<31, GENERAL, 2>(K);
+    return emax <= 15 ? chunk_wave_bytes_t<15, GENERAL>(K) : chunk_wave_bytes_t<31, GENERAL>(K);
 }
 
 template <int EMAX, bool GENERAL>
@@ -876,10 +867,9 @@ size_t filter_lds_bytes(uint32_t waves_per_block, uint32_t wmax) {
     return (size_t)waves_per_block * 2 * wmax * kLdsRow * sizeof(uint64_t);
 }
 
-size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_t chunk_tiles, uint32_t lpp,
-                       bool keyed) {
-    return (size_t)waves_per_block * (general ? chunk_bytes_for<true>(emax, chunk_tiles, lpp, keyed)
-                                              : chunk_bytes_for<false>(emax, chunk_tiles, lpp, keyed));
+size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_t chunk_tiles, uint32_t lpp) {
+    return (size_t)waves_per_block * (general ? chunk_bytes_for<true>(emax, chunk_tiles, lpp)
+                                              : chunk_bytes_for<false>(emax, chunk_tiles, lpp));
 }
 
 hipError_t launch_filter(const FilterParams& p, Engine eng, bool general, int emax,

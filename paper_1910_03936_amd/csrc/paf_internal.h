@@ -99,10 +99,8 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 const void* filter_kernel_ptr(Engine eng, bool general, int emax, uint32_t filters);
 const void* whole_kernel_ptr(bool general, int emax, uint32_t filters);
 size_t filter_lds_bytes(uint32_t waves_per_block, uint32_t wmax);
-// LDS of a compacting launch; keyed launches (order_key set) also hold the
-// sort buffer.
-size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_t chunk_tiles, uint32_t lpp,
-                       bool keyed);
+// LDS of a compacting launch (keyed launches sort inside the list itself).
+size_t chunk_lds_bytes(uint32_t waves_per_block, bool general, int emax, uint32_t chunk_tiles, uint32_t lpp);
 
 // verify.hip: banded edit distance of the selected pairs (sel: accept-bit
 // words, or NULL for every pair).
