@@ -118,14 +118,17 @@ def kernel_source_hash(kernel: str = "snake_chunk") -> str:
 
 def traffic_record(key: str, path: str | None = None):
     """HBM bytes per launch measured with rocprofv3 counters, if they were taken
-    on the current kernel sources (else None)."""
+    on the current sources of the record's kernel (else None).  Keys name the
+    kernel first: `key_levels_...` records hold the levels kernel, the others
+    the compacting filter."""
     path = path or os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     r = rec.get(key)
-    if not r or r.get("kernel_sha256_16") != kernel_source_hash():
+    kernel = "key_levels" if key.startswith("key_levels") else "snake_chunk"
+    if not r or r.get("kernel_sha256_16") != kernel_source_hash(kernel):
         return None
     return r
 
@@ -578,6 +581,12 @@ def main():
                    "vs_plain": round(plain_ms / learned_ms, 3), "identical_decisions": same,
                    "stages_ms": {"features+model (levels)": round(model_ms, 4),
                                  "compacting filter, chunks ordered by level": round(keyed_ms, 4)},
+                   # The levels stage on its own line: five words read per
+                   # pair (three of the read, two of the reference) and one
+                   # byte written.
+                   "levels_roofline": roof(model_ms, 5 * 8 + 1,
+                                           f"key_kernel<E={args.E}, two sets> (features, gate, bf16 MLP, level)",
+                                           f"key_levels_250bp_E{args.E}"),
                    "level_sizes": hist.cpu().tolist(),
                    "keyed_filter_ms_by_key": ablation,
                    "per_tile_engine_ms_by_order": per_tile,

@@ -80,7 +80,7 @@ def test_record_traffic_from_counter_csvs(tmp_path):
 
 def test_traffic_record_used_only_for_matching_sources(tmp_path):
     """bench.traffic_record returns a record only while its hash matches the
-    current kernel sources."""
+    current sources of the kernel the record's key names."""
     good = {"kernel_sha256_16": bench.kernel_source_hash("snake_chunk"), "n_pairs": 1, "bytes_per_launch": 1.0}
     stale = dict(good, kernel_sha256_16="0" * 16)
     path = tmp_path / "hbm_traffic.json"
@@ -89,3 +89,10 @@ def test_traffic_record_used_only_for_matching_sources(tmp_path):
     assert bench.traffic_record("b", str(path)) is None
     assert bench.traffic_record("c", str(path)) is None
     assert bench.traffic_record("a", str(tmp_path / "missing.json")) is None
+    # A levels-kernel record is checked against the levels kernel's sources.
+    lv = {"kernel_sha256_16": bench.kernel_source_hash("key_levels"), "n_pairs": 1, "bytes_per_launch": 2.0}
+    path.write_text(json.dumps({"key_levels_250bp_E10": lv, "key_levels_250bp_E5": good,
+                                "snake_chunk_plain_250bp_E10": lv}))
+    assert bench.traffic_record("key_levels_250bp_E10", str(path)) == lv
+    assert bench.traffic_record("key_levels_250bp_E5", str(path)) is None
+    assert bench.traffic_record("snake_chunk_plain_250bp_E10", str(path)) is None
