@@ -93,6 +93,30 @@ def test_chunk_edge_lengths_and_thresholds(ctx):
     ctx.check()
 
 
+@pytest.mark.parametrize("unrelated", [0.0, 0.5, 0.7])
+def test_keyed_sort_taken_and_skipped(ctx, unrelated):
+    """Keyed launches sort a chunk's first-pass survivors by key class only
+    while they fill at most half of the chunk's list.  Related pairs only
+    (nearly all accepted, so nearly all survive the first 64 columns and
+    every chunk skips the sort), an even mix (chunks on both sides of half)
+    and the benchmark's 70% unrelated mix (about 30% survive: sorted), each
+    under several chunk sizes, against the oracle."""
+    w = pairgen.Workload("keyed sort", 64 * 53 + 7, (250,), 8, unrelated, fixed_E=10, seed=4242)
+    p = pairgen.generate(w, 0, w.n_pairs)
+    want = oracle_for(p, SS)
+    if unrelated == 0.0:
+        # An accepted pair is still undecided after the first pass (64 of
+        # its 250 columns).
+        assert float((np.asarray(want[SS][0]) == 1).mean()) > 0.99
+    b = to_device(p, ctx, per_pair=False, offsets=False)
+    g = torch.Generator().manual_seed(3)
+    key = torch.randint(0, 16, (p.n,), generator=g, dtype=torch.uint8).cuda()
+    for lay in (None, _layout(2, 0, 6, 2, 3), _layout(2, 0, 2, 2, 3), _layout(4, 2, 16, 1, 2)):
+        ctx.set_layout(lay)
+        assert_parity(results(ctx.filter_keyed(b, key), p.n), want, f"keyed unrelated={unrelated} {lay}")
+    ctx.check()
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 511, 512, 513])
 def test_chunk_tiny_batches(ctx, n):
     p = pairgen.generate(pairgen.FIXED_250BP, 300, n)
