@@ -133,6 +133,25 @@ def traffic_record(key: str, path: str | None = None):
     return r
 
 
+# Chunk-size and pass-width sweep of the compacting filter (the first entry is
+# the layout paf_filter picks by itself at max_E 9..15).
+LAYOUT_SWEEP = "2,6,2,3;2,8,2,3;2,4,2,3;4,4,2,3;2,3,2,3;2,2,2,3;2,6,3,3"
+
+
+def parse_layouts(spec: str) -> list:
+    """'W,K,F,P;...' -> paf_layout dicts (one lane per pair, full grid)."""
+    out = []
+    for part in spec.split(";"):
+        wpb, k, f, p = (int(x) for x in part.split(","))
+        out.append({"lanes_per_pair": 1, "waves_per_block": wpb, "blocks_per_cu": 0, "tiles_per_grab": 1,
+                    "chunk_tiles": k, "first_pass_windows": f, "pass_windows": p})
+    return out
+
+
+def layout_tuple(lay: dict) -> list:
+    return [lay["waves_per_block"], lay["chunk_tiles"], lay["first_pass_windows"], lay["pass_windows"]]
+
+
 def counter_run(args):
     """One kind of launch, repeated, for rocprofv3 counter runs: `plain` is the
     compacting filter alone; `keyed` trains the cost model on --train-pairs
@@ -155,12 +174,17 @@ def counter_run(args):
     else:
         costmodel.train(ctx, w, n=args.train_pairs, epochs=4, batch=4096, lr=2e-3)
         step = lambda: ctx.filter_keyed(batch, ctx.cost_levels(batch), out=out)
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
+    layouts = parse_layouts(args.layout) if args.layout else [None]
+    for lay in layouts:
+        # With several layouts the dispatches come in this order, --steps each.
+        ctx.set_layout(lay)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+    ctx.set_layout(None)
     ctx.check()
-    print(json.dumps({"counter_run": args.counter_run, "n_pairs": n, "E": args.E, "launches": args.steps}),
-          flush=True)
+    print(json.dumps({"counter_run": args.counter_run, "n_pairs": n, "E": args.E, "launches": args.steps,
+                      "layouts": [layout_tuple(l) for l in layouts if l is not None]}), flush=True)
 
 
 def _counter_csv(path):
@@ -382,7 +406,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="fixed250",
                     choices=["fixed250", "filters", "partitioned", "verify", "accuracy", "uneven", "learned-uneven",
-                             "stream"],
+                             "stream", "layouts"],
                     help="fixed250 (default): 10M x 250 bp at E (plain and learned-bucketed); filters: the "
                          "same pairs at E = 0, 5, 10, 25 with SneakySnake, GateKeeper, Shouji and all three "
                          "on one map; uneven: 50M pairs of mixed lengths in the persistent launch, default "
@@ -392,7 +416,7 @@ def main():
                          "at E = 0, 5, 10, 25; verify: banded edit distance of the pairs SneakySnake accepts "
                          "(filter + verify) vs verifying every pair, at E = 5, 10, 25; accuracy: false accept "
                          "and false reject rates of every filter against the exact banded distance, at E = 0, 5, "
-                         "10, 25")
+                         "10, 25; layouts: the plain filter at E under each forced compacting layout (--layout)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain copy kernel of known size (counter calibration)")
     ap.add_argument("--calibrate-hbm", action="store_true",
@@ -402,6 +426,10 @@ def main():
     ap.add_argument("--reps", type=int, default=3, help="timed repetitions of each calibration kernel")
     ap.add_argument("--counter-run", choices=["plain", "keyed"], default=None,
                     help="only launch one kind of filter step --steps times (for rocprofv3 counter runs)")
+    ap.add_argument("--layout", default=None, metavar="W,K,F,P[;...]",
+                    help="forced compacting layouts (waves per block, tiles per chunk, first / later pass "
+                         "windows): --counter-run plain launches each in turn, --workload layouts times "
+                         "each (default: the chunk-size sweep)")
     ap.add_argument("--record-traffic", metavar="DIR", default=None,
                     help="write profiles/hbm_traffic.json from the counter runs under DIR (no GPU)")
     ap.add_argument("--record-out", metavar="PATH", default=None,
@@ -447,6 +475,9 @@ def main():
         return
     if args.workload in ("partitioned", "verify", "accuracy"):
         next_workloads(args)
+        return
+    if args.workload == "layouts":
+        layouts_workload(args)
         return
     if args.workload != "fixed250":
         other_workload(args)
@@ -640,6 +671,44 @@ def main():
     }
     print(json.dumps(rec), flush=True)
     ctx.close()
+
+
+def layouts_workload(args):
+    """10M x 250 bp at E: the plain compacting filter under each forced layout,
+    timed with HIP events after a clock ramp, outputs compared with the
+    filter's own choice."""
+    import torch
+
+    import pairgen
+    import paper_1910_03936_amd as paf
+
+    dev = torch.device("cuda", 0)
+    ctx = paf.Context(0)
+    w = pairgen.FIXED_250BP.with_E(args.E)
+    n = args.pairs or w.n_pairs
+    batch, _ = build_batch(ctx, w, n, dev)
+    SS = paf.SNEAKYSNAKE
+    ref = ctx.filter(batch, SS)
+    out = ctx.alloc_out(n, SS, dev)
+    rows = []
+    for lay in parse_layouts(args.layout or LAYOUT_SWEEP):
+        ctx.set_layout(lay)
+        step = lambda: ctx.filter(batch, SS, out=out)
+        ramp(step)
+        per, total, _ = time_steps(step, args.steps, args.warmup)
+        same = all(torch.equal(out[SS][j], ref[SS][j]) for j in range(2))
+        rows.append({"layout": layout_tuple(lay), "ms": round(total / args.steps, 4),
+                     "ms_median": round(sorted(per)[len(per) // 2], 4), "identical": same})
+        log(f"layout {layout_tuple(lay)} (waves per block, tiles per chunk, first / later pass windows): "
+            f"{total / args.steps:.4f} ms, identical outputs: {same}")
+    ctx.set_layout(None)
+    ctx.check()
+    best = min(rows, key=lambda r: r["ms"])
+    emit(args, n / (rows[0]["ms"] / 1e3), rows[0]["ms"],
+         f"{n} pairs, 250 bp, 2-bit packed, E={args.E}, 70% unrelated, k~U{{0..40}}; plain SneakySnake under "
+         f"forced compacting layouts (value: the first)",
+         {"pairs": n, "read_len": 250, "E": args.E}, None, None,
+         {"layouts": rows, "fastest": best["layout"]})
 
 
 def emit(args, metric_value, ms, workload_desc, cfg, roofline, cpu, extra):

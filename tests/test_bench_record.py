@@ -96,3 +96,11 @@ def test_traffic_record_used_only_for_matching_sources(tmp_path):
     assert bench.traffic_record("key_levels_250bp_E10", str(path)) == lv
     assert bench.traffic_record("key_levels_250bp_E5", str(path)) is None
     assert bench.traffic_record("snake_chunk_plain_250bp_E10", str(path)) is None
+
+
+def test_layout_list_parsing():
+    """--layout 'W,K,F,P;...' becomes forced paf_layout dicts in order."""
+    lays = bench.parse_layouts("2,6,2,3;4,4,1,2")
+    assert [bench.layout_tuple(l) for l in lays] == [[2, 6, 2, 3], [4, 4, 1, 2]]
+    assert all(l["lanes_per_pair"] == 1 and l["blocks_per_cu"] == 0 and l["tiles_per_grab"] == 1 for l in lays)
+    assert bench.layout_tuple(bench.parse_layouts(bench.LAYOUT_SWEEP)[0]) == [2, 6, 2, 3]
