@@ -148,11 +148,12 @@ paf_status paf_pack_ascii(const char* seqs, uint32_t row_stride, const uint16_t*
  * fast path plus amended shifted masks (Ch. 5, Sec. 5.2) and Shouji's
  * sliding-window search (Ch. 6, Sec. 6.2).  filters: mask of PAF_* bits.
  * SneakySnake alone runs on the compacting engine (see paf_layout's
- * chunk_tiles; a first pass of 2 windows, then: up to max_E 3, 4 waves per
- * block, chunks of 4 tiles and later passes of 3 windows; 4..6: 2 waves, 4
- * tiles, 3 windows; 7..8: 2 waves, 6 tiles, 2 windows; 9..15: 2 waves, 6
- * tiles, 3 windows; above: 2 waves, 6 tiles, 2 windows; unless a layout was
- * forced with paf_set_layout,
+ * chunk_tiles; up to max_E 15 a first pass of 2 windows, then: up to max_E
+ * 3, 4 waves per block, chunks of 4 tiles and later passes of 3 windows;
+ * 4..6: 2 waves, 4 tiles, 3 windows; 7..8: 2 waves, 6 tiles, 2 windows;
+ * 9..15: 2 waves, 6 tiles, 3 windows; 16..25: 2 waves, 6 tiles, a first
+ * pass of 3 windows, then 1; above: the same with a first pass of 4; unless
+ * a layout was forced with paf_set_layout,
  * whose waves_per_block, chunk_tiles and pass widths then apply here too;
  * chunk_tiles = 0 selects the per-tile engine).  Several stages share one
  * map and one launch up to max_E 7; from max_E 8 SneakySnake runs as above in a launch of its own,
