@@ -42,11 +42,12 @@ def test_small_100bp_full_snake(gpu_ctx):
     gpu_ctx.check()
 
 
-@pytest.mark.parametrize("E", [0, 5, 10, 25])
+@pytest.mark.parametrize("E", [0, 5, 10, 20, 25, 31])
 def test_fixed_250bp_all_filters(gpu_ctx, E):
-    """250 bp at each threshold: SneakySnake alone (lazy engine) and all three
-    filters on the same map (whole-map engine); 3001 pairs = 46 full tiles and
-    a ragged tail."""
+    """250 bp at each threshold: SneakySnake alone (compacting engine, in the
+    default layout of each threshold class, up to the longer first pass and
+    one-window later passes above 15) and all three filters in one call;
+    3001 pairs = 46 full tiles and a ragged tail."""
     p = pairgen.generate(pairgen.FIXED_250BP.with_E(E), 0, 3001)
     b = to_device(p, gpu_ctx, per_pair=False, offsets=False)
     want = oracle_for(p, ALL)
