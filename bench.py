@@ -922,6 +922,9 @@ def next_workloads(args):
         torch.cuda.synchronize()
 
     def timed(fn):
+        # A clock ramp before each timed call: a call timed right after the
+        # short E = 0 launches would otherwise run at lower clocks.
+        ramp(fn, 0.2)
         per, _, _ = time_steps(fn, steps, args.warmup)
         ctx.check()
         return sum(per) / len(per)

@@ -179,8 +179,9 @@ paf_status paf_filter(paf_ctx* ctx, const paf_batch* batch, uint32_t filters, co
  * either), and t >= m with y = 0 gives paf_filter's SneakySnake result.
  * t in [1, PAF_MAX_PART].  Writes out->accept_bits[0] and out->count[0] (the
  * SneakySnake slots; the others are ignored).  Runs on the compacting engine
- * with paf_filter's layout (a forced layout applies when its chunk_tiles >
- * 0). */
+ * with paf_filter's layout, except that from max_E 4 to 6 it takes chunks of
+ * 6 tiles and later passes of 1 window (a forced layout applies when its
+ * chunk_tiles > 0). */
 #define PAF_MAX_PART 65535
 #define PAF_MAX_REPL 31
 paf_status paf_filter_partitioned(paf_ctx* ctx, const paf_batch* batch, uint32_t t, uint32_t y,
