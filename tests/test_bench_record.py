@@ -104,3 +104,16 @@ def test_layout_list_parsing():
     assert [bench.layout_tuple(l) for l in lays] == [[2, 6, 2, 3], [4, 4, 1, 2]]
     assert all(l["lanes_per_pair"] == 1 and l["blocks_per_cu"] == 0 and l["tiles_per_grab"] == 1 for l in lays)
     assert bench.layout_tuple(bench.parse_layouts(bench.LAYOUT_SWEEP)[0]) == [2, 6, 2, 3]
+
+
+def test_more_than_one_gpu_is_refused():
+    """bench.py measures one GPU: --gpus above 1, or a launch with several
+    ranks, exits with status 2 and says so before touching a device."""
+    env = dict(os.environ)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, env=env)
+    assert r.returncode == 2 and "one GPU only" in r.stderr
+    env["WORLD_SIZE"] = "2"
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")],
+                       capture_output=True, text=True, timeout=120, env=env)
+    assert r.returncode == 2 and "one GPU only" in r.stderr
