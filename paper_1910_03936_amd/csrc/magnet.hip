@@ -464,6 +464,11 @@ hipError_t launch_magnet(const FilterParams& p, int emax, uint8_t* flag, uint32_
         hipError_t e = hipLaunchKernel(kt, dim3(blocks), dim3(64 * waves), args, lds_t, s);
         if (e != hipSuccess) return e;
     }
+    // With max_E 0 the first test decides every pair (only a pair equal to
+    // its reference is accepted): no list to build and nothing to extract.
+    if (emax == 0)
+        return launch_accept_from_counts(p.cnt[0], p.len, p.uniform_len, p.E, p.uniform_E, p.max_len, p.max_E,
+                                         p.n_pairs, p.acc[0], s);
     // Undecided pairs first (flag 0), in pair order.
     hipError_t e = launch_bucket_sort(flag, p.n_pairs, counts, order, hist, s);
     if (e != hipSuccess) return e;

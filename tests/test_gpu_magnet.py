@@ -64,7 +64,8 @@ def test_magnet_edge_lengths(gpu_ctx):
     Ev = np.zeros(n, np.uint8)
     for i, (a, r, m, E) in enumerate(rows):
         R[i, :m], F[i, :m], L[i], Ev[i] = a, r, m, E
-    for me in (7, 15, 31):
+    # max_E 0: the first test decides every pair (no list, no extraction).
+    for me in (0, 7, 15, 31):
         sel = np.nonzero(Ev <= me)[0]
         q = pairgen.Pairs(R[sel], F[sel], L[sel], Ev[sel], np.zeros(sel.size, np.uint8),
                           np.zeros(sel.size, np.uint16))
